@@ -1,0 +1,248 @@
+"""FP64 CPU oracle for grouped full-spectrum fitting -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its binding) never loads it.  The C source shares no code with the HIP
+library.
+
+Python side: ctypes marshalling only; every number comes from
+``lasp_oracle.c``.  Calls release the GIL, so a thread pool fits spectra in
+parallel.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lasp_oracle.c")
+_LIB = os.path.join(_HERE, "liblasp_oracle.so")
+
+NONFINITE, NO_DATA, SINGULAR, CONT_NONPOS, OUT_OF_BOX, NOT_CONVERGED = (1 << i for i in range(6))
+N_PAR = 5
+N_BASIS = 20
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-fno-fast-math", "-std=c11", "-Wall", "-shared", "-fPIC",
+                        _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("n_pix", ctypes.c_int),
+        ("margin", ctypes.c_int),
+        ("degree", ctypes.c_int),
+        ("n_arms", ctypes.c_int),
+        ("arm_start", ctypes.c_int * 4),
+        ("arm_sigma", ctypes.c_double * 4),
+        ("dlog10", ctypes.c_double),
+        ("lo", ctypes.c_double * 5),
+        ("hi", ctypes.c_double * 5),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.POINTER(ctypes.c_float)
+        ip = ctypes.POINTER(ctypes.c_int)
+        up = ctypes.POINTER(ctypes.c_uint)
+        cp = ctypes.POINTER(_Cfg)
+        lib.orc_features.argtypes = [dp, dp, dp]
+        lib.orc_features.restype = None
+        lib.orc_legendre.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.orc_legendre.restype = ctypes.c_double
+        lib.orc_kernel.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        lib.orc_kernel.restype = ctypes.c_int
+        lib.orc_convolve.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, dp]
+        lib.orc_convolve.restype = None
+        lib.orc_eval.argtypes = [cp, fp, fp, fp, dp, dp, dp, dp, dp, dp, ip, dp, dp, up]
+        lib.orc_eval.restype = ctypes.c_int
+        lib.orc_residual.argtypes = [cp, fp, fp, fp, dp, dp, dp, dp]
+        lib.orc_residual.restype = ctypes.c_int
+        lib.orc_fit.argtypes = [cp, fp, fp, fp, dp, ctypes.c_int, dp, dp, dp, ip, dp, dp, ip, up]
+        lib.orc_fit.restype = ctypes.c_int
+        lib.orc_covariance.argtypes = [cp, fp, fp, fp, dp, dp, dp]
+        lib.orc_covariance.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _d(a):
+    return _p(a, ctypes.c_double)
+
+
+def _f(a):
+    return _p(a, ctypes.c_float)
+
+
+class Config:
+    """Grid/shape description for the oracle (plain values, no arithmetic)."""
+
+    def __init__(self, n_pix, margin, degree, dlog10, box_lo, box_hi, arm_start=(), arm_sigma=()):
+        c = _Cfg()
+        c.n_pix, c.margin, c.degree = int(n_pix), int(margin), int(degree)
+        c.n_arms = len(arm_start)
+        for i, (s, g) in enumerate(zip(arm_start, arm_sigma)):
+            c.arm_start[i] = int(s)
+            c.arm_sigma[i] = float(g)
+        c.dlog10 = float(dlog10)
+        for i in range(5):
+            c.lo[i] = float(box_lo[i])
+            c.hi[i] = float(box_hi[i])
+        self.c = c
+        self.n_pix, self.margin, self.degree = c.n_pix, c.margin, c.degree
+        self.n_ext = c.n_pix + 2 * c.margin
+        self.box_lo = np.array(box_lo, dtype=np.float64)
+        self.box_hi = np.array(box_hi, dtype=np.float64)
+
+    @classmethod
+    def from_shape(cls, shape, box_lo, box_hi):
+        return cls(shape.n_pix, shape.margin, shape.degree, shape.dlog10, box_lo, box_hi,
+                   shape.arm_start, shape.arm_sigma_kms)
+
+    def normalise(self, phys):
+        """Physical (Teff K, logg, [Fe/H], RV, sigma) -> u in the box [-1, 1]."""
+        phys = np.asarray(phys, dtype=np.float64)
+        th = phys.copy()
+        th[..., 0] = np.log10(phys[..., 0])
+        return 2.0 * (th - self.box_lo) / (self.box_hi - self.box_lo) - 1.0
+
+    def physical(self, u):
+        u = np.asarray(u, dtype=np.float64)
+        th = self.box_lo + 0.5 * (u + 1.0) * (self.box_hi - self.box_lo)
+        th[..., 0] = 10.0 ** th[..., 0]
+        return th
+
+
+def features(x):
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    phi = np.empty(N_BASIS)
+    dphi = np.empty((3, N_BASIS))
+    lib.orc_features(_d(x), _d(phi), _d(dphi))
+    return phi, dphi
+
+
+def legendre(n, x):
+    return _load().orc_legendre(int(n), float(x))
+
+
+def kernel(mu, sig, margin):
+    lib = _load()
+    n = 2 * margin + 1
+    G, Gm, Gs = np.zeros(n), np.zeros(n), np.zeros(n)
+    H = lib.orc_kernel(float(mu), float(sig), int(margin), _d(G), _d(Gm), _d(Gs))
+    T = 2 * H + 1
+    return H, G[:T].copy(), Gm[:T].copy(), Gs[:T].copy()
+
+
+def convolve(fp, G, margin, n_pix):
+    lib = _load()
+    fp = np.ascontiguousarray(fp, dtype=np.float64)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    H = (G.size - 1) // 2
+    out = np.zeros(n_pix)
+    lib.orc_convolve(_d(fp), fp.size, _d(G), H, int(margin), 0, int(n_pix), _d(out))
+    return out
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def evaluate(cfg: Config, obs, ivar, basis, u):
+    """Model at fixed normalised u for one spectrum; dict of FP64 results."""
+    lib = _load()
+    obs, ivar, basis = _f32(obs), _f32(ivar), _f32(basis)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    P, nd = cfg.n_pix, cfg.degree + 1
+    out = dict(fp=np.empty(cfg.n_ext), fpp=np.empty(P), b=np.empty(nd), model=np.empty(P),
+               grad=np.empty(5), jac=np.empty((5, P)))
+    chi2 = ctypes.c_double()
+    neff = ctypes.c_int()
+    flags = ctypes.c_uint()
+    rc = lib.orc_eval(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u), _d(out["fp"]),
+                      _d(out["fpp"]), _d(out["b"]), _d(out["model"]), ctypes.byref(chi2),
+                      ctypes.byref(neff), _d(out["grad"]), _d(out["jac"]), ctypes.byref(flags))
+    out.update(rc=rc, chi2=chi2.value, n_eff=neff.value, flags=flags.value)
+    out["J"] = chi2.value / neff.value if neff.value > 0 else float("nan")
+    return out
+
+
+def residual(cfg: Config, obs, ivar, basis, u, b, want_jac=True):
+    lib = _load()
+    obs, ivar, basis = _f32(obs), _f32(ivar), _f32(basis)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    r = np.empty(cfg.n_pix)
+    jac = np.empty((cfg.n_pix, 5 + cfg.degree + 1)) if want_jac else None
+    lib.orc_residual(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u), _d(b), _d(r), _d(jac))
+    return (r, jac) if want_jac else r
+
+
+def fit(cfg: Config, obs, ivar, basis, u0, max_iter=200):
+    """Levenberg-Marquardt fit of one spectrum from normalised start u0."""
+    lib = _load()
+    obs, ivar, basis = _f32(obs), _f32(ivar), _f32(basis)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    u = np.empty(5)
+    b = np.empty(cfg.degree + 1)
+    cov_u = np.empty((5, 5))
+    cov_p = np.empty((5, 5))
+    chi2 = ctypes.c_double()
+    neff = ctypes.c_int()
+    nit = ctypes.c_int()
+    flags = ctypes.c_uint()
+    rc = lib.orc_fit(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u0), int(max_iter),
+                     _d(u), _d(b), ctypes.byref(chi2), ctypes.byref(neff), _d(cov_u), _d(cov_p),
+                     ctypes.byref(nit), ctypes.byref(flags))
+    return dict(rc=rc, u=u, b=b, chi2=chi2.value, n_eff=neff.value, cov_u=cov_u, cov=cov_p,
+                n_iter=nit.value, flags=flags.value, params=cfg.physical(u))
+
+
+def covariance(cfg: Config, obs, ivar, basis, u):
+    lib = _load()
+    obs, ivar, basis = _f32(obs), _f32(ivar), _f32(basis)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    cov_u = np.empty((5, 5))
+    cov_p = np.empty((5, 5))
+    rc = lib.orc_covariance(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u), _d(cov_u),
+                            _d(cov_p))
+    return dict(rc=rc, cov_u=cov_u, cov=cov_p)
+
+
+def fit_many(cfg: Config, obs, ivar, basis, init_phys, max_iter=200, threads=None):
+    """Fit each row independently on a thread pool; returns a list of dicts."""
+    n = obs.shape[0]
+    u0 = cfg.normalise(init_phys)
+    threads = threads or os.cpu_count() or 1
+    basis = _f32(basis)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(fit, cfg, obs[i], ivar[i], basis, u0[i], max_iter) for i in range(n)]
+        return [f.result() for f in futs]
