@@ -1,0 +1,158 @@
+/*
+ * lasp.h -- C ABI of the MI355X grouped full-spectrum fitting library.
+ *
+ * The library fits, for N spectra at once, the model of the paper's
+ * LASP-Adam-GPU method (arXiv 2512.24840, Section 2.2):
+ *   Eq. 1  model spectrum from a polynomial interpolator, F' = Phi(theta) B
+ *   Eq. 5  Gaussian velocity shift and broadening, F'' = F' (x) G(mu, sigma)
+ *   Eq. 6  multiplicative polynomial continuum fitted by weighted least squares
+ *   Eq. 7  residual, and Eq. 9 objective read per spectrum as chi2 / n_eff
+ *   stage 8 Adam on the five parameters normalised to [-1, 1]
+ *   stage 9 parameter covariance by linear error propagation
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers (HIP global memory) unless marked
+ *    HOST.  They are owned by the caller, C-contiguous, row-major.  The
+ *    library reads and writes them only from work it enqueues on
+ *    opts->stream and never keeps them past that work.
+ *  - Calls are stream ordered: they return once the work is enqueued (after
+ *    host-side validation); results are valid after the stream is
+ *    synchronised.  Internal scratch memory (per device and stream) is cached
+ *    between calls and returned by lasp_release().  Two calls that overlap on
+ *    the same stream are ordered; calls on different streams use separate
+ *    scratch.
+ *  - Parameters, physical units: (Teff [K], log g [dex], [Fe/H] [dex],
+ *    RV [km/s], sigma [km/s]).  Normalised parameters u in [-1, 1]:
+ *    u_t = 2 (theta_t - lo_t) / (hi_t - lo_t) - 1 with theta = (log10 Teff,
+ *    log g, [Fe/H], RV, sigma) and the box opts->box_lo / box_hi.  The fit
+ *    does not clamp u to the box.
+ *  - Return value: LASP_OK (0) or a negative LASP_E_* code; the message of
+ *    the last failure on the calling thread is lasp_last_error().  No entry
+ *    point aborts or throws.
+ */
+#ifndef LASP_H
+#define LASP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LASP_OK 0
+#define LASP_E_ARG (-1)         /* null pointer, bad dimension or option */
+#define LASP_E_GRID (-2)        /* wave_grid not uniform in log10(lambda) */
+#define LASP_E_DEVICE (-3)      /* HIP runtime or launch error */
+#define LASP_E_NOMEM (-4)       /* device allocation failed */
+#define LASP_E_UNSUPPORTED (-5) /* shape/precision without a compiled kernel */
+
+/* Per-spectrum status bits (opts->status).  One spectrum's status never
+ * changes another spectrum's results. */
+#define LASP_ST_NONFINITE_INPUT 0x01u /* some obs/ivar not finite: pixel weight set to 0 */
+#define LASP_ST_NO_DATA 0x02u         /* n_eff <= 5 + degree + 1 */
+#define LASP_ST_SINGULAR 0x04u        /* continuum normal equations not positive definite */
+#define LASP_ST_CONT_NONPOS 0x08u     /* fitted continuum P(x) b <= 0 at some pixel */
+#define LASP_ST_OUT_OF_BOX 0x10u      /* final |u_t| > 1.5 for some parameter */
+#define LASP_ST_SIGMA_FLOOR 0x20u     /* broadening width at the 0.1 px floor */
+
+#define LASP_PREC_FP32 0   /* FP32 interpolator contraction */
+#define LASP_PREC_BF16X3 1 /* BF16 hi/lo split contraction, FP32 accumulate */
+
+#define LASP_N_BASIS 20 /* monomials of total degree <= 3 in (u1, u2, u3) */
+#define LASP_N_PAR 5
+#define LASP_MAX_ARMS 4
+
+/*
+ * Options.  Fill with lasp_default_opts() and override.
+ *  n_spec, n_pix   number of spectra B and pixels P per spectrum.
+ *  n_basis         must be LASP_N_BASIS; basis row k multiplies monomial k of
+ *                  (u1, u2, u3) in graded lexicographic order:
+ *                  1, u1, u2, u3, u1^2, u1u2, u1u3, u2^2, u2u3, u3^2, u1^3,
+ *                  u1^2u2, u1^2u3, u1u2^2, u1u2u3, u1u3^2, u2^3, u2^2u3,
+ *                  u2u3^2, u3^3.
+ *  margin          M: the basis covers P + 2M pixels, column c <-> pixel c-M.
+ *  degree          continuum degree D; compiled: 4, 6, 8, 10.
+ *  precision       LASP_PREC_FP32 or LASP_PREC_BF16X3.
+ *  box_lo, box_hi  normalisation box (see above).
+ *  lr, beta1, beta2, eps   Adam hyper-parameters (torch.optim.Adam form).
+ *  weight_quantile flux quantile used as the per-spectrum weight w of Eq. 6
+ *                  (Section 3.3: 0.5); <= 0 uses w = 1.  The objective is
+ *                  invariant to w; it only conditions the arithmetic.
+ *  n_arms, arm_start, arm_sigma_kms   optional spectrograph arms: pixel j in
+ *                  arm a is broadened by sqrt(sigma^2 + arm_sigma_kms[a]^2).
+ *                  n_arms = 0: one arm, no instrumental term.
+ *  stream          hipStream_t to enqueue on (NULL: the null stream).
+ *  status          optional device uint32 [n_spec]: LASP_ST_* bits.
+ *  out_chi2        optional device double [n_spec]: chi2 at the returned
+ *                  parameters (weights ivar, data obs).
+ */
+typedef struct lasp_opts {
+  int32_t n_spec;
+  int32_t n_pix;
+  int32_t n_basis;
+  int32_t margin;
+  int32_t degree;
+  int32_t precision;
+  double box_lo[LASP_N_PAR];
+  double box_hi[LASP_N_PAR];
+  float lr, beta1, beta2, eps;
+  float weight_quantile;
+  int32_t n_arms;
+  int32_t arm_start[LASP_MAX_ARMS];
+  float arm_sigma_kms[LASP_MAX_ARMS];
+  void *stream;
+  uint32_t *status;
+  double *out_chi2;
+} lasp_opts;
+
+/* Defaults: n_basis 20, margin 64, degree 10, FP32, box
+ * lo = (log10 4000, 1, -2.5, -300, 50), hi = (log10 8000, 5, 0.5, 300, 150),
+ * lr 1e-2, betas (0.9, 0.999), eps 1e-8, weight_quantile 0.5, no arms,
+ * null stream, no status/chi2 outputs.  n_spec and n_pix are set to 0. */
+void lasp_default_opts(lasp_opts *opts);
+
+/*
+ * Grouped fit (Section 2.2, stages 2-9): n_steps Adam steps on every
+ * spectrum's chi2 / n_eff, then optionally the covariance.
+ *   obs          [B][P] float   observed flux (any scale)
+ *   ivar         [B][P] float   inverse variance; <= 0 or non-finite masks a pixel
+ *   wave_grid    HOST [P] double  pixel wavelengths (A); must be uniform in
+ *                log10 to 1e-6 of the step, else LASP_E_GRID
+ *   basis        [20][P+2M] float interpolator coefficient spectra
+ *   init_params  [B][5] float   start, physical units
+ *   out_params   [B][5] float   result, physical units (may alias init_params)
+ *   out_cov      [B][5][5] double covariance in physical units, or NULL
+ *   n_steps      >= 0 Adam steps
+ * Returns LASP_OK or a LASP_E_* code.
+ */
+int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
+                   const float *basis, const float *init_params, float *out_params,
+                   double *out_cov, int32_t n_steps, const lasp_opts *opts);
+
+/*
+ * Model at fixed normalised parameters (one forward pass and its adjoint).
+ *   u         [B][5] float normalised parameters
+ *   out_model [B][P] float  C (.) F'' in the units of obs, or NULL
+ *   out_chi2  [B] double    chi2 (required)
+ *   out_neff  [B] int32     pixels with positive weight, or NULL
+ *   out_grad  [B][5] float  d(chi2/n_eff)/du with the continuum held at its
+ *             least-squares value (envelope theorem), or NULL
+ *   out_jac   [B][5][P] float d model / d u at fixed continuum, or NULL
+ * Other arguments as in lasp_fit_group (opts->out_chi2 is ignored).
+ */
+int lasp_forward(const float *obs, const float *ivar, const double *wave_grid,
+                 const float *basis, const float *u, float *out_model, double *out_chi2,
+                 int32_t *out_neff, float *out_grad, float *out_jac, const lasp_opts *opts);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *lasp_last_error(void);
+
+/* Frees all cached device scratch memory on every device. */
+void lasp_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LASP_H */

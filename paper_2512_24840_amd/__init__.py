@@ -1,0 +1,17 @@
+"""MI355X-native grouped full-spectrum fitting (LASP-Adam-GPU hot path).
+
+The HIP library ``_lib/liblasp.so`` (sources in ``csrc/``, ABI in
+``include/lasp.h``) does all arithmetic; ``lasp`` is its ctypes binding.
+"""
+
+from .lasp import (  # noqa: F401
+    Arms,
+    DEFAULT_BOX,
+    FitResult,
+    LaspError,
+    fit_group,
+    forward,
+    library_path,
+    load,
+    release,
+)

@@ -1,0 +1,485 @@
+// Parameter covariance at the final point (Section 2.2 stage 9: linear
+// error propagation Sigma = s^2 (J^T J)^{-1} with s^2 = chi2 / (n_eff - 5)).
+//
+// The residual r_j = sqrt(W_j) (o_j - C_j F''_j) depends on the five
+// parameters u and on the continuum coefficients b.  The u-block of the
+// inverse normal matrix is the inverse of the Schur complement
+//   S = Ju^T Ju - Ju^T Jb (Jb^T Jb)^{-1} Jb^T Ju,
+// so with Jb^T Jb = A (the continuum Gram matrix) and X = Jb^T Ju only 5x5
+// and (D+1)x5 sums are needed.  The five columns dF''/du are formed in
+// forward mode: dF''/du_t = G (x) dF'/du_t for t = 1..3 (dF'/du_t from the
+// derivative rows of the interpolator contraction) and
+// dF''/du_{4,5} = (dG/dmu, dG/dsigma) (x) F' times the chain factors.
+// Optionally the model Jacobian d(C F'')/du at fixed continuum is written.
+#include "lasp_internal.h"
+
+namespace lasp {
+namespace {
+
+constexpr int kOffF = 16;
+
+struct CovLayout {
+  int ks;
+  int k_off;   // floats: taps [n_arms][3][ks]
+  int d_off;   // bytes: doubles
+  int bytes;
+};
+
+__host__ __device__ inline CovLayout cov_layout(const Geometry &g, int nwaves) {
+  CovLayout L;
+  L.ks = ((2 * g.M + 1 + 7) & ~7) + 8;
+  const int sf_len = kOffF + g.ldF + 32;
+  L.k_off = (sf_len + 3) & ~3;
+  const int fl_end = L.k_off + g.n_arms * 3 * L.ks;
+  L.d_off = ((fl_end * 4) + 15) & ~15;
+  // doubles: reduction [nwaves][64], moments [64], JuJu [32], X [16][8],
+  // work [64], scalars [16]
+  L.bytes = L.d_off + 8 * (nwaves * 64 + 64 + 32 + 128 + 64 + 16);
+  return L;
+}
+
+template <int BLOCK, int ND>
+__global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0, double bhi0,
+                                               double blo1, double bhi1, double blo2, double bhi2,
+                                               double out_scale3, double out_scale4,
+                                               double *out_cov, float *out_jac) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int NNU = 2 * ND - 1;
+  constexpr int NMOM = NNU + ND;
+  constexpr int NWIN = kNPL + kTB - 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const CovLayout L = cov_layout(g, NW);
+  float *sF = reinterpret_cast<float *>(smem);
+  float *sK = sF + L.k_off;
+  double *sRed = reinterpret_cast<double *>(smem + L.d_off);
+  double *sMom = sRed + NW * 64;
+  double *sJJ = sMom + 64;
+  double *sX = sJJ + 32;      // [ND][5]
+  double *sW = sX + 128;      // work
+  double *sScal = sW + 64;
+  float *sBf = reinterpret_cast<float *>(sScal);       // [16] (b as float)
+  int *sHa = reinterpret_cast<int *>(sScal + 8);        // [kMaxArms]
+  float *sCs = reinterpret_cast<float *>(sScal + 12);   // [kMaxArms] chain factor for sigma
+
+  const int spec = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int P = g.P, M = g.M;
+  const int j0 = tid * kNPL;
+  const bool has_pix = j0 < P;
+  const bool multi = g.n_arms > 1;
+
+  // ---- taps G, dG/dmu, dG/dsigma per arm ---------------------------------
+  const float u4 = s.u[(size_t)spec * kNP + 3];
+  const float u5 = s.u[(size_t)spec * kNP + 4];
+  const float rv = g.rv_lo + (u4 + 1.f) * g.rv_half;
+  const float sg = g.sg_lo + (u5 + 1.f) * g.sg_half;
+  const float mu = rv * g.inv_scale;
+  const float cmu = g.rv_half * g.inv_scale;
+  if (wave == 0) {
+    for (int a = 0; a < g.n_arms; ++a) {
+      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
+      float spx = seff * g.inv_scale;
+      const bool fl = !(spx >= kSigmaFloorPx);
+      if (fl) spx = kSigmaFloorPx;
+      float hf = ceilf(fabsf(mu) + 5.f * spx);
+      if (!(hf <= (float)M)) hf = (float)M;
+      const int H = (int)hf, T = 2 * H + 1;
+      double gv[3], dv[3];
+      double part = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int idx = lane + 64 * k;
+        double v = 0.0, d = 0.0;
+        if (idx < T) {
+          d = (double)(idx - H) - (double)mu;
+          v = exp(-d * d / (2.0 * (double)spx * (double)spx));
+        }
+        gv[k] = v;
+        dv[k] = d;
+        part += v;
+      }
+      const double inv_sum = 1.0 / wave_sum(part);
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        gv[k] *= inv_sum;
+        s1 += gv[k] * dv[k];
+        s2 += gv[k] * dv[k] * dv[k];
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      const double sp = (double)spx;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int idx = lane + 64 * k;
+        if (idx < L.ks) {
+          const bool in = idx < T;
+          sK[(a * 3 + 0) * L.ks + idx] = in ? (float)gv[k] : 0.f;
+          sK[(a * 3 + 1) * L.ks + idx] = in ? (float)(gv[k] * (dv[k] - s1) / (sp * sp)) : 0.f;
+          sK[(a * 3 + 2) * L.ks + idx] =
+              in ? (float)(gv[k] * (dv[k] * dv[k] - s2) / (sp * sp * sp)) : 0.f;
+        }
+      }
+      if (lane == 0) {
+        sHa[a] = H;
+        sCs[a] = fl ? 0.f : g.sg_half * g.inv_scale * (g.bare ? 1.f : sg / seff);
+      }
+    }
+  }
+
+  // ---- forward-mode columns: F'' and dF''/du_t, one staged row at a time --
+  float f[kNPL], d[kNP][kNPL];
+#pragma unroll
+  for (int i = 0; i < kNPL; ++i) {
+    f[i] = 0.f;
+#pragma unroll
+    for (int t = 0; t < kNP; ++t) d[t][i] = 0.f;
+  }
+  const int wp0 = wave * 64 * kNPL;
+  const int wp1 = min(wp0 + 64 * kNPL, P) - 1;
+  int wa_lo = 0, wa_hi = 0;
+  for (int a = 1; a < g.n_arms; ++a) {
+    if (g.arm_start[a] <= wp0) wa_lo = a;
+    if (g.arm_start[a] <= wp1) wa_hi = a;
+  }
+  for (int row = 0; row < 4; ++row) {
+    __syncthreads();
+    {
+      const float4 *src =
+          reinterpret_cast<const float4 *>(s.fp + (size_t)spec * s.fp_stride + (size_t)row * g.ldF);
+      for (int q = tid; q < g.ldF / 4; q += BLOCK)
+        *reinterpret_cast<float4 *>(sF + kOffF + 4 * q) = src[q];
+      for (int q = tid; q < kOffF; q += BLOCK) sF[q] = 0.f;
+      for (int q = tid; q < 32; q += BLOCK) sF[kOffF + g.ldF + q] = 0.f;
+    }
+    __syncthreads();
+    if (!has_pix) continue;
+    for (int a = wa_lo; a <= wa_hi; ++a) {
+      const int H = sHa[a], T = 2 * H + 1;
+      const int nk = row == 0 ? 3 : 1;  // row 0 also gives the mu and sigma columns
+      float acc[3][kNPL];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int i = 0; i < kNPL; ++i) acc[q][i] = 0.f;
+      for (int mb = 0; mb < T; mb += kTB) {
+        const float *wsrc = sF + kOffF + j0 + M + H - mb - (kTB - 1);
+        float w[NWIN];
+#pragma unroll
+        for (int q = 0; q < NWIN; ++q) w[q] = wsrc[q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (q < nk) {
+            const float *K = sK + (a * 3 + q) * L.ks;
+#pragma unroll
+            for (int t = 0; t < kTB; ++t) {
+              const float gk = K[mb + t];
+#pragma unroll
+              for (int i = 0; i < kNPL; ++i) acc[q][i] = fmaf(gk, w[i - t + kTB - 1], acc[q][i]);
+            }
+          }
+        }
+      }
+      const int lo = multi ? g.arm_start[a] : 0;
+      const int hi = multi ? g.arm_start[a + 1] : 0x7fffffff;
+      const float cs = sCs[a];
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i) {
+        if (j0 + i >= lo && j0 + i < hi) {
+          if (row == 0) {
+            f[i] = acc[0][i];
+            d[3][i] = cmu * acc[1][i];
+            d[4][i] = cs * acc[2][i];
+          } else {
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+              if (row == t + 1) d[t][i] = acc[0][i];
+          }
+        }
+      }
+    }
+  }
+
+  float2 ow[kNPL];
+  {
+    const float2 *src = s.ow + (size_t)spec * kNPL * BLOCK + tid;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) ow[i] = src[i * BLOCK];
+  }
+
+  // ---- continuum least squares at the final point (as in the fused pass) --
+  {
+    double acc[NMOM];
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) acc[k] = 0.0;
+    const double two_over_p = 2.0 / (double)P;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      const double x = fma((double)(j0 + i), two_over_p, -1.0);
+      const double wf = (double)ow[i].y * (double)f[i];
+      const double y = wf * (double)f[i];
+      const double z = wf * (double)ow[i].x;
+      double tm = 1.0, tc = x;
+      acc[0] += y;
+      acc[1] = fma(y, x, acc[1]);
+      acc[NNU] += z;
+      acc[NNU + 1] = fma(z, x, acc[NNU + 1]);
+#pragma unroll
+      for (int l = 2; l < NNU; ++l) {
+        const double tn = fma(x + x, tc, -tm);
+        acc[l] = fma(y, tn, acc[l]);
+        if (l < ND) acc[NNU + l] = fma(z, tn, acc[NNU + l]);
+        tm = tc;
+        tc = tn;
+      }
+    }
+    block_sum_doubles<NW, NMOM>(acc, sRed, sMom, lane, wave);
+  }
+  if (wave == 0) {
+    double a[ND + 1];
+    const bool row = lane < ND;
+#pragma unroll
+    for (int n = 0; n < ND; ++n) {
+      const int dd = lane > n ? lane - n : n - lane;
+      a[n] = row ? 0.5 * (sMom[min(lane + n, NNU - 1)] + sMom[min(dd, NNU - 1)]) : 0.0;
+    }
+    a[ND] = row ? sMom[NNU + min(lane, ND - 1)] : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      double piv[ND + 1];
+#pragma unroll
+      for (int n = k; n <= ND; ++n) piv[n] = __shfl(a[n], k, 64);
+      ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
+      const double rp = 1.0 / piv[k];
+      if (lane == k) {
+#pragma unroll
+        for (int n = k; n <= ND; ++n) a[n] *= rp;
+      } else {
+        const double fct = a[k] * rp;
+#pragma unroll
+        for (int n = k + 1; n <= ND; ++n) a[n] = fma(-fct, piv[n], a[n]);
+        a[k] = 0.0;
+      }
+    }
+    if (row) sBf[lane] = ok ? (float)a[ND] : 0.f;
+    if (lane == 0) sScal[15] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  // ---- residual Jacobian columns ju_t = C dF''/du_t; chi2 ------------------
+  float C[kNPL];
+  double chi2_part = 0.0;
+  {
+    float c[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) c[k] = sBf[k];
+    const float two_over_p = 2.f / (float)P;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      const float x = fmaf((float)(j0 + i), two_over_p, -1.f);
+      float b1 = 0.f, b2 = 0.f;
+#pragma unroll
+      for (int k = ND - 1; k >= 1; --k) {
+        const float bk = fmaf(x + x, b1, c[k] - b2);
+        b2 = b1;
+        b1 = bk;
+      }
+      C[i] = fmaf(x, b1, c[0] - b2);
+      const float e = ow[i].x - C[i] * f[i];
+      chi2_part = fma((double)(ow[i].y * e), (double)e, chi2_part);
+#pragma unroll
+      for (int t = 0; t < kNP; ++t) d[t][i] *= C[i];
+    }
+  }
+  if (out_jac) {
+    const float wsc = s.wscale[spec];
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i)
+      if (j0 + i < P)
+#pragma unroll
+        for (int t = 0; t < kNP; ++t)
+          out_jac[((size_t)spec * kNP + t) * P + j0 + i] = d[t][i] * wsc;
+  }
+  if (out_cov == nullptr) return;
+
+  // Ju^T Ju (15 entries, FP64) and chi2
+  {
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      const double w = (double)ow[i].y;
+      int k = 0;
+#pragma unroll
+      for (int p = 0; p < kNP; ++p)
+#pragma unroll
+        for (int q = 0; q <= p; ++q) acc[k++] += w * (double)d[p][i] * (double)d[q][i];
+    }
+    acc[15] = chi2_part;
+    block_sum_doubles<NW, 16>(acc, sRed, sJJ, lane, wave);
+  }
+  // X[n][t] = Jb^T Ju = sum W F'' T_n ju_t (Chebyshev T_n)
+#pragma unroll 1
+  for (int t = 0; t < kNP; ++t) {
+    double acc[ND];
+#pragma unroll
+    for (int n = 0; n < ND; ++n) acc[n] = 0.0;
+    const double two_over_p = 2.0 / (double)P;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      float dti = d[0][i];
+#pragma unroll
+      for (int q = 1; q < kNP; ++q)
+        if (q == t) dti = d[q][i];
+      const double x = fma((double)(j0 + i), two_over_p, -1.0);
+      const double v = (double)ow[i].y * (double)f[i] * (double)dti;
+      double tm = 1.0, tc = x;
+      acc[0] += v;
+      acc[1] = fma(v, x, acc[1]);
+#pragma unroll
+      for (int n = 2; n < ND; ++n) {
+        const double tn = fma(x + x, tc, -tm);
+        acc[n] = fma(v, tn, acc[n]);
+        tm = tc;
+        tc = tn;
+      }
+    }
+    block_sum_doubles<NW, ND>(acc, sRed, sW, lane, wave);
+    if (tid < ND) sX[tid * kNP + t] = sW[tid];
+    __syncthreads();
+  }
+
+  // ---- wave 0: Y = A^{-1} X, S = JuJu - X^T Y, Sigma_u = s^2 S^{-1} --------
+  if (wave == 0) {
+    constexpr int NC = ND + kNP;
+    double a[NC];
+    const bool row = lane < ND;
+#pragma unroll
+    for (int n = 0; n < ND; ++n) {
+      const int dd = lane > n ? lane - n : n - lane;
+      a[n] = row ? 0.5 * (sMom[min(lane + n, NNU - 1)] + sMom[min(dd, NNU - 1)]) : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kNP; ++t) a[ND + t] = row ? sX[min(lane, ND - 1) * kNP + t] : 0.0;
+    bool ok = sScal[15] != 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      double piv[NC];
+#pragma unroll
+      for (int n = k; n < NC; ++n) piv[n] = __shfl(a[n], k, 64);
+      ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
+      const double rp = 1.0 / piv[k];
+      if (lane == k) {
+#pragma unroll
+        for (int n = k; n < NC; ++n) a[n] *= rp;
+      } else {
+        const double fct = a[k] * rp;
+#pragma unroll
+        for (int n = k + 1; n < NC; ++n) a[n] = fma(-fct, piv[n], a[n]);
+        a[k] = 0.0;
+      }
+    }
+    if (row) {
+#pragma unroll
+      for (int t = 0; t < kNP; ++t) sW[lane * kNP + t] = a[ND + t];  // Y[n][t]
+    }
+    if (lane == 0) sScal[14] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    bool ok = sScal[14] != 0.0;
+    // lanes 0..4 own rows of S, then invert S by Gauss-Jordan on [S | I]
+    double sr[2 * kNP];
+    const int r = lane < kNP ? lane : 0;
+#pragma unroll
+    for (int q = 0; q < kNP; ++q) {
+      const int p = r > q ? r : q, qq = r > q ? q : r;
+      double v = sJJ[p * (p + 1) / 2 + qq];
+#pragma unroll
+      for (int n = 0; n < ND; ++n) v -= sX[n * kNP + r] * sW[n * kNP + q];
+      sr[q] = v;
+      sr[kNP + q] = (r == q) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kNP; ++k) {
+      double piv[2 * kNP];
+#pragma unroll
+      for (int n = 0; n < 2 * kNP; ++n) piv[n] = __shfl(sr[n], k, 64);
+      ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
+      const double rp = 1.0 / piv[k];
+      if (lane == k) {
+#pragma unroll
+        for (int n = 0; n < 2 * kNP; ++n) sr[n] *= rp;
+      } else {
+        const double fct = sr[k] * rp;
+#pragma unroll
+        for (int n = 0; n < 2 * kNP; ++n) sr[n] = fma(-fct, piv[n], sr[n]);
+      }
+    }
+    const int n_eff = s.neff[spec];
+    const double chi2 = sJJ[15];
+    const double s2 = n_eff > kNP ? chi2 / (double)(n_eff - kNP) : NAN;
+    if (lane < kNP) {
+      // physical units: Teff via dTeff = Teff ln10 dlog10Teff, the others by
+      // the box half-widths
+      const double lt = blo0 + 0.5 * ((double)s.u[(size_t)spec * kNP] + 1.0) * (bhi0 - blo0);
+      double jd[kNP];
+      jd[0] = 0.5 * (bhi0 - blo0) * exp10(lt) * kLn10;
+      jd[1] = 0.5 * (bhi1 - blo1);
+      jd[2] = 0.5 * (bhi2 - blo2);
+      jd[3] = out_scale3;
+      jd[4] = out_scale4;
+      double jr = jd[0];
+#pragma unroll
+      for (int q = 1; q < kNP; ++q)
+        if (q == lane) jr = jd[q];
+#pragma unroll
+      for (int q = 0; q < kNP; ++q) {
+        const double v = ok ? s2 * sr[kNP + q] * jr * jd[q] : NAN;
+        out_cov[((size_t)spec * kNP + lane) * kNP + q] = v;
+      }
+    }
+    if (lane == 0 && !ok) s.status[spec] |= kStSingular;
+  }
+}
+
+template <int BLOCK, int ND>
+hipError_t launch_cov_t(const Geometry &g, const State &s, const double *lo, const double *hi,
+                        double *out_cov, float *out_jac, hipStream_t st) {
+  const CovLayout L = cov_layout(g, BLOCK / 64);
+  auto k = k_cov<BLOCK, ND>;
+  hipError_t e =
+      hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, lo[0], hi[0], lo[1], hi[1],
+                     lo[2], hi[2], 0.5 * (hi[3] - lo[3]), 0.5 * (hi[4] - lo[4]), out_cov, out_jac);
+  return hipGetLastError();
+}
+
+template <int BLOCK>
+hipError_t launch_cov_b(const Geometry &g, const State &s, const double *lo, const double *hi,
+                        double *out_cov, float *out_jac, hipStream_t st) {
+  switch (g.nd) {
+    case 5: return launch_cov_t<BLOCK, 5>(g, s, lo, hi, out_cov, out_jac, st);
+    case 7: return launch_cov_t<BLOCK, 7>(g, s, lo, hi, out_cov, out_jac, st);
+    case 9: return launch_cov_t<BLOCK, 9>(g, s, lo, hi, out_cov, out_jac, st);
+    case 11: return launch_cov_t<BLOCK, 11>(g, s, lo, hi, out_cov, out_jac, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cov(const Geometry &g, const State &s, const double *lo, const double *hi,
+                      double *out_cov, float *out_jac, hipStream_t st) {
+  switch (g.block) {
+    case 128: return launch_cov_b<128>(g, s, lo, hi, out_cov, out_jac, st);
+    case 256: return launch_cov_b<256>(g, s, lo, hi, out_cov, out_jac, st);
+    case 512: return launch_cov_b<512>(g, s, lo, hi, out_cov, out_jac, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lasp

@@ -1,0 +1,512 @@
+// Fused per-spectrum pass of one Adam step (Section 2.2, stages 4-8):
+//   Eq. 5  Gaussian kernel G(mu, sigma) and F'' = F' (x) G, F' staged in LDS
+//   Eq. 6  continuum by weighted least squares: moments of W F''^2 and
+//          W F'' o against Chebyshev polynomials, normal equations solved
+//          in FP64 (Gauss-Jordan, one lane per row)
+//   Eq. 7  residual e = o - C F'';  Eq. 9 chi2 = sum W e^2 (per spectrum)
+//   adjoint of J = chi2 / n_eff with the continuum at its least-squares
+//          value (envelope theorem): g_j = -2 W e C / n_eff, the lag
+//          correlation R(m) = sum_j g_j F'_{j-m+M} giving dJ/dmu and
+//          dJ/dsigma, and the transposed convolution F-bar' that the
+//          backward contraction turns into dJ/du_{1..3}.
+//
+// The continuum space {polynomials of degree <= D} is spanned here by
+// Chebyshev polynomials: the least-squares fit, its residual, chi2 and the
+// gradient are the same as with the paper's Legendre basis (only the
+// coefficient vector differs), and T_m T_n = (T_{m+n} + T_{|m-n|}) / 2
+// turns the Gram matrix into 2D + 1 moments.
+//
+// One workgroup owns one spectrum; lane l owns pixels [17 l, 17 l + 17) (an
+// odd stride, so lanes hit distinct LDS banks).  Taps run in register blocks
+// of 8 against a 24-value window.
+#include "lasp_internal.h"
+
+namespace lasp {
+namespace {
+
+constexpr int kOffF = 16;  // F' column c lives at sF[kOffF + c]
+
+struct FusedLayout {
+  int sf_len;     // floats
+  int gb_off;     // float offset of the g-bar row (logical pixel j at gb_off + gb_base + j)
+  int gb_base;    // 2M
+  int gb_len;
+  int ks;         // taps buffer stride per arm
+  int k_off;      // float offset of the taps
+  int r_off;      // float offset of per-wave R(m) partials [NW][n_arms][ks]
+  int rs_off;     // float offset of R(m) sums [n_arms][ks]
+  int d_off;      // byte offset of the double scratch
+  int bytes;
+};
+
+__host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwaves, int nmom_pad) {
+  FusedLayout L;
+  L.sf_len = kOffF + g.ldF + 32;
+  L.gb_base = 2 * g.M;
+  L.gb_len = g.P + 4 * g.M + 32;
+  L.gb_off = (L.sf_len + 3) & ~3;
+  L.ks = ((2 * g.M + 1 + 7) & ~7) + 8;
+  L.k_off = (L.gb_off + L.gb_len + 3) & ~3;
+  L.r_off = L.k_off + g.n_arms * L.ks;
+  L.rs_off = L.r_off + nwaves * g.n_arms * L.ks;
+  int fl_end = L.rs_off + g.n_arms * L.ks;
+  L.d_off = ((fl_end * 4) + 15) & ~15;
+  // doubles: reduction scratch [nwaves][64], moments [nmom_pad], b [32],
+  // scalars [32] (flag, float b copy, per-arm H and sigma)
+  L.bytes = L.d_off + 8 * (nwaves * 64 + nmom_pad + 32 + 32);
+  return L;
+}
+
+template <int BLOCK, int ND, bool ADJ>
+__global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *model_out) {
+  constexpr int NW = BLOCK / 64;
+  constexpr int NNU = 2 * ND - 1;  // nu_0 .. nu_{2D}
+  constexpr int NMOM = NNU + ND;   // plus r_0 .. r_D
+  constexpr int NWIN = kNPL + kTB - 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const FusedLayout L = fused_layout(g, NW, NMOM);
+  float *sF = reinterpret_cast<float *>(smem);
+  float *sGb = sF + L.gb_off + L.gb_base;  // sGb[j], j in [-2M, P + 2M + 32)
+  float *sK = sF + L.k_off;
+  float *sRp = sF + L.r_off;
+  float *sRs = sF + L.rs_off;
+  double *sRed = reinterpret_cast<double *>(smem + L.d_off);
+  double *sMom = sRed + NW * 64;
+  double *sBd = sMom + NMOM;
+  double *sScal = sBd + 32;
+  float *sBf = reinterpret_cast<float *>(sScal + 8);  // [16]
+  int *sHa = reinterpret_cast<int *>(sScal + 16);      // [kMaxArms]
+  float *sSp = reinterpret_cast<float *>(sScal + 20);  // [kMaxArms]
+
+  const int spec = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int P = g.P, M = g.M;
+  const int j0 = tid * kNPL;           // first pixel (and basis column) of this lane
+  const bool has_pix = j0 < P;
+  const int jr = has_pix ? j0 : 0;     // window origin kept in range for idle lanes
+
+  // ---- stage F' into LDS, clear the g-bar row and the pads --------------
+  {
+    const float4 *src = reinterpret_cast<const float4 *>(s.fp + (size_t)spec * s.fp_stride);
+    for (int q = tid; q < g.ldF / 4; q += BLOCK)
+      *reinterpret_cast<float4 *>(sF + kOffF + 4 * q) = src[q];
+    for (int q = tid; q < kOffF; q += BLOCK) sF[q] = 0.f;
+    for (int q = tid; q < 32; q += BLOCK) sF[kOffF + g.ldF + q] = 0.f;
+    for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
+    for (int q = tid; q < NW * g.n_arms * L.ks; q += BLOCK) sRp[q] = 0.f;
+  }
+
+  // ---- Eq. 5 kernel parameters: mu, sigma in pixels, H per arm ----------
+  const float u4 = s.u[(size_t)spec * kNP + 3];
+  const float u5 = s.u[(size_t)spec * kNP + 4];
+  const float rv = g.rv_lo + (u4 + 1.f) * g.rv_half;
+  const float sg = g.sg_lo + (u5 + 1.f) * g.sg_half;
+  const float mu = rv * g.inv_scale;
+  if (wave == 0) {
+    for (int a = 0; a < g.n_arms; ++a) {
+      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
+      float spx = seff * g.inv_scale;
+      if (!(spx >= kSigmaFloorPx)) spx = kSigmaFloorPx;
+      float hf = ceilf(fabsf(mu) + 5.f * spx);
+      if (!(hf <= (float)M)) hf = (float)M;  // also catches NaN
+      const int H = (int)hf, T = 2 * H + 1;
+      const float inv2s2 = 0.5f / (spx * spx);
+      float gv[3];
+      float part = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int idx = lane + 64 * k;
+        float v = 0.f;
+        if (idx < T) {
+          const float d = (float)(idx - H) - mu;
+          v = expf(-d * d * inv2s2);
+        }
+        gv[k] = v;
+        part += v;
+      }
+      const float inv_sum = 1.f / wave_sum(part);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int idx = lane + 64 * k;
+        if (idx < L.ks) sK[a * L.ks + idx] = gv[k] * inv_sum;
+      }
+      if (lane == 0) {
+        sHa[a] = H;
+        sSp[a] = spx;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- arms touched by this wave's output pixels (wave uniform) ---------
+  const bool multi = g.n_arms > 1;
+  const int wp0 = wave * 64 * kNPL;
+  const int wp1 = min(wp0 + 64 * kNPL, P) - 1;
+  int wa_lo = 0, wa_hi = 0;
+  for (int a = 1; a < g.n_arms; ++a) {
+    if (g.arm_start[a] <= wp0) wa_lo = a;
+    if (g.arm_start[a] <= wp1) wa_hi = a;
+  }
+
+  // ---- Eq. 5: F''_j = sum_m G(m) F'_{j-m+M} ------------------------------
+  float fpp[kNPL];
+#pragma unroll
+  for (int i = 0; i < kNPL; ++i) fpp[i] = 0.f;
+  if (has_pix) {
+    for (int a = wa_lo; a <= wa_hi; ++a) {
+      const int H = sHa[a], T = 2 * H + 1;
+      const float *K = sK + a * L.ks;
+      float acc[kNPL];
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i) acc[i] = 0.f;
+      for (int mb = 0; mb < T; mb += kTB) {
+        const float *wsrc = sF + kOffF + j0 + M + H - mb - (kTB - 1);
+        float w[NWIN];
+#pragma unroll
+        for (int q = 0; q < NWIN; ++q) w[q] = wsrc[q];
+#pragma unroll
+        for (int t = 0; t < kTB; ++t) {
+          const float gk = K[mb + t];
+#pragma unroll
+          for (int i = 0; i < kNPL; ++i) acc[i] = fmaf(gk, w[i - t + kTB - 1], acc[i]);
+        }
+      }
+      if (!multi) {
+#pragma unroll
+        for (int i = 0; i < kNPL; ++i) fpp[i] = acc[i];
+      } else {
+        const int lo = g.arm_start[a], hi = g.arm_start[a + 1];
+#pragma unroll
+        for (int i = 0; i < kNPL; ++i)
+          if (j0 + i >= lo && j0 + i < hi) fpp[i] = acc[i];
+      }
+    }
+  }
+
+  // ---- data (lane-major, coalesced); zero beyond P ------------------------
+  float2 ow[kNPL];
+  {
+    const float2 *src = s.ow + (size_t)spec * kNPL * BLOCK + tid;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) ow[i] = src[i * BLOCK];
+  }
+
+  // ---- Eq. 6 moments in FP64: nu_l = sum W F''^2 T_l, r_n = sum W F'' o T_n
+  {
+    double acc[NMOM];
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) acc[k] = 0.0;
+    const double two_over_p = 2.0 / (double)P;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      const double x = fma((double)(j0 + i), two_over_p, -1.0);
+      const double f = (double)fpp[i];
+      const double wf = (double)ow[i].y * f;
+      const double y = wf * f;
+      const double z = wf * (double)ow[i].x;
+      double tm = 1.0, tc = x;
+      acc[0] += y;
+      acc[1] = fma(y, x, acc[1]);
+      acc[NNU] += z;
+      acc[NNU + 1] = fma(z, x, acc[NNU + 1]);
+      const double x2 = x + x;
+#pragma unroll
+      for (int l = 2; l < NNU; ++l) {
+        const double tn = fma(x2, tc, -tm);
+        acc[l] = fma(y, tn, acc[l]);
+        if (l < ND) acc[NNU + l] = fma(z, tn, acc[NNU + l]);
+        tm = tc;
+        tc = tn;
+      }
+    }
+    block_sum_doubles<NW, NMOM>(acc, sRed, sMom, lane, wave);
+  }
+
+  // ---- normal equations A b = r (A_mn = (nu_{m+n} + nu_|m-n|)/2), solved
+  //      in FP64 by Gauss-Jordan elimination, lane i holding row i --------
+  if (wave == 0) {
+    double a[ND + 1];
+    const bool row = lane < ND;
+#pragma unroll
+    for (int n = 0; n < ND; ++n) {
+      const int d = lane > n ? lane - n : n - lane;
+      a[n] = row ? 0.5 * (sMom[min(lane + n, NNU - 1)] + sMom[min(d, NNU - 1)]) : 0.0;
+    }
+    a[ND] = row ? sMom[NNU + min(lane, ND - 1)] : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      double piv[ND + 1];
+#pragma unroll
+      for (int n = k; n <= ND; ++n) piv[n] = __shfl(a[n], k, 64);
+      ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
+      const double rp = 1.0 / piv[k];
+      if (lane == k) {
+#pragma unroll
+        for (int n = k; n <= ND; ++n) a[n] *= rp;
+      } else {
+        const double f = a[k] * rp;
+#pragma unroll
+        for (int n = k + 1; n <= ND; ++n) a[n] = fma(-f, piv[n], a[n]);
+        a[k] = 0.0;
+      }
+    }
+    if (row) {
+      const double bi = ok ? a[ND] : 0.0;
+      sBd[lane] = bi;
+      sBf[lane] = (float)bi;
+    }
+    if (lane == 0) sScal[0] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  // ---- Eq. 7 residual, Eq. 9 chi2, adjoint seed g = dJ/dF'' ---------------
+  const bool ok = sScal[0] != 0.0;
+  const int n_eff = s.neff[spec];
+  const float inv_neff = n_eff > 0 ? 1.f / (float)n_eff : 0.f;
+  const float wsc = s.wscale[spec];
+  float gb[kNPL];
+  double chi2_part = 0.0;
+  float cmin = INFINITY;
+  {
+    float c[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) c[k] = sBf[k];
+    const float two_over_p = 2.f / (float)P;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      const int j = j0 + i;
+      const float x = fmaf((float)j, two_over_p, -1.f);
+      const float x2 = x + x;
+      float b1 = 0.f, b2 = 0.f;
+#pragma unroll
+      for (int k = ND - 1; k >= 1; --k) {
+        const float bk = fmaf(x2, b1, c[k] - b2);
+        b2 = b1;
+        b1 = bk;
+      }
+      const float C = fmaf(x, b1, c[0] - b2);  // Clenshaw sum of c_k T_k(x)
+      const float mdl = C * fpp[i];
+      const float e = ow[i].x - mdl;
+      const float we = ow[i].y * e;
+      chi2_part = fma((double)we, (double)e, chi2_part);
+      gb[i] = ok ? -2.f * we * C * inv_neff : 0.f;
+      if (j < P) {
+        cmin = fminf(cmin, C);
+        if (model_out) model_out[(size_t)spec * P + j] = mdl * wsc;
+        if (ADJ) sGb[j] = gb[i];
+      }
+    }
+  }
+  {
+    const double cs = wave_sum(chi2_part);
+    const float cm = wave_min(cmin);
+    if (lane == 0) {
+      sRed[wave * 64 + 0] = cs;
+      sRed[wave * 64 + 1] = (double)cm;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double cs = 0.0, cm = INFINITY;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      cs += sRed[w * 64 + 0];
+      cm = fmin(cm, sRed[w * 64 + 1]);
+    }
+    s.chi2[spec] = cs;
+    uint32_t st = s.status[spec];
+    if (!ok) st |= kStSingular;
+    if (!(cm > 0.0)) st |= kStContNonpos;
+    for (int a = 0; a < g.n_arms; ++a) {
+      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
+      if (!(seff * g.inv_scale >= kSigmaFloorPx)) st |= kStSigmaFloor;
+    }
+    s.status[spec] = st;
+  }
+  if (!ADJ) return;
+
+  // ---- lag correlation R_a(m) = sum_{j in arm a} g_j F'_{j-m+M} ----------
+  if (wp0 < P) {
+    for (int a = wa_lo; a <= wa_hi; ++a) {
+      const int H = sHa[a], T = 2 * H + 1;
+      float gm[kNPL];
+      if (!multi) {
+#pragma unroll
+        for (int i = 0; i < kNPL; ++i) gm[i] = has_pix ? gb[i] : 0.f;
+      } else {
+        const int lo = g.arm_start[a], hi = g.arm_start[a + 1];
+#pragma unroll
+        for (int i = 0; i < kNPL; ++i)
+          gm[i] = (has_pix && j0 + i >= lo && j0 + i < hi) ? gb[i] : 0.f;
+      }
+      for (int mb = 0; mb < T; mb += kTB) {
+        const float *wsrc = sF + kOffF + jr + M + H - mb - (kTB - 1);
+        float w[NWIN];
+#pragma unroll
+        for (int q = 0; q < NWIN; ++q) w[q] = wsrc[q];
+        float r[kTB];
+#pragma unroll
+        for (int t = 0; t < kTB; ++t) {
+          float acc = 0.f;
+#pragma unroll
+          for (int i = 0; i < kNPL; ++i) acc = fmaf(gm[i], w[i - t + kTB - 1], acc);
+          r[t] = acc;
+        }
+        const float rs = wave_reduce_scatter<kTB, float>(r, lane);
+        if ((lane & 7) == 0) sRp[(wave * g.n_arms + a) * L.ks + mb + (lane >> 3)] = rs;
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < g.n_arms * L.ks; q += BLOCK) {
+    float acc = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) acc += sRp[w * g.n_arms * L.ks + q];
+    sRs[q] = acc;
+  }
+  __syncthreads();
+
+  // ---- dJ/dmu, dJ/dsigma per arm and the chain to u4, u5 (wave 0) -------
+  if (wave == 0) {
+    double g4 = 0.0, g5 = 0.0;
+    for (int a = 0; a < g.n_arms; ++a) {
+      const int H = sHa[a], T = 2 * H + 1;
+      double s1 = 0, s2 = 0, rg = 0, rgd = 0, rgd2 = 0;
+      for (int idx = lane; idx < T; idx += 64) {
+        const double d = (double)(idx - H) - (double)mu;
+        const double G = (double)sK[a * L.ks + idx];
+        const double R = (double)sRs[a * L.ks + idx];
+        s1 += G * d;
+        s2 += G * d * d;
+        rg += R * G;
+        rgd += R * G * d;
+        rgd2 += R * G * d * d;
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      rg = wave_sum(rg);
+      rgd = wave_sum(rgd);
+      rgd2 = wave_sum(rgd2);
+      const double sp = (double)sSp[a];
+      const double dmu = (rgd - s1 * rg) / (sp * sp);
+      const double dsig = (rgd2 - s2 * rg) / (sp * sp * sp);
+      g4 += dmu * (double)g.rv_half * (double)g.inv_scale;
+      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
+      const bool fl = !(seff * g.inv_scale >= kSigmaFloorPx);
+      const double dsdu = fl ? 0.0
+                             : (double)g.sg_half * (double)g.inv_scale *
+                                   (g.bare ? 1.0 : (double)sg / (double)seff);
+      g5 += dsig * dsdu;
+    }
+    if (lane == 0) {
+      s.g45[(size_t)spec * 2 + 0] = ok ? (float)g4 : 0.f;
+      s.g45[(size_t)spec * 2 + 1] = ok ? (float)g5 : 0.f;
+    }
+  }
+
+  // ---- transposed convolution F-bar'_c = sum_m G(m) g_{c+m-M} ------------
+  const int c0 = j0;
+  float fb[kNPL];
+#pragma unroll
+  for (int i = 0; i < kNPL; ++i) fb[i] = 0.f;
+  if (c0 < g.Pe) {
+    // arms whose pixels the columns of this wave can reach (wave uniform)
+    int ta_lo = 0, ta_hi = 0;
+    if (multi) {
+      const int jlo = wave * 64 * kNPL - 2 * M;
+      const int jhi = (wave + 1) * 64 * kNPL - 1;
+      for (int a = 1; a < g.n_arms; ++a) {
+        if (g.arm_start[a] <= jlo) ta_lo = a;
+        if (g.arm_start[a] <= jhi) ta_hi = a;
+      }
+    }
+    for (int a = ta_lo; a <= ta_hi; ++a) {
+      const int H = sHa[a], T = 2 * H + 1;
+      const float *K = sK + a * L.ks;
+      const int lo = multi ? g.arm_start[a] : 0;
+      const int hi = multi ? g.arm_start[a + 1] : P;
+      for (int mb = 0; mb < T; mb += kTB) {
+        const int base = c0 - H + mb - M;
+        float w[NWIN];
+#pragma unroll
+        for (int q = 0; q < NWIN; ++q) w[q] = sGb[base + q];
+        if (multi) {
+#pragma unroll
+          for (int q = 0; q < NWIN; ++q) w[q] = (base + q >= lo && base + q < hi) ? w[q] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < kTB; ++t) {
+          const float gk = K[mb + t];
+#pragma unroll
+          for (int i = 0; i < kNPL; ++i) fb[i] = fmaf(gk, w[i + t], fb[i]);
+        }
+      }
+    }
+  }
+  __syncthreads();  // every read of F' in sF is done
+#pragma unroll
+  for (int i = 0; i < kNPL; ++i)
+    if (c0 + i < g.ldF) sF[kOffF + c0 + i] = (c0 + i < g.Pe) ? fb[i] : 0.f;
+  __syncthreads();
+  {
+    float4 *dst = reinterpret_cast<float4 *>(s.fbar + (size_t)spec * g.ldF);
+    for (int q = tid; q < g.ldF / 4; q += BLOCK)
+      dst[q] = *reinterpret_cast<const float4 *>(sF + kOffF + 4 * q);
+  }
+}
+
+template <int BLOCK, int ND>
+hipError_t launch_fused_t(const Geometry &g, const State &s, int adjoint, float *model_out,
+                          hipStream_t st) {
+  const FusedLayout L = fused_layout(g, BLOCK / 64, 3 * ND - 1);
+  if (adjoint) {
+    auto k = k_fused<BLOCK, ND, true>;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       L.bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, model_out);
+  } else {
+    auto k = k_fused<BLOCK, ND, false>;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       L.bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, model_out);
+  }
+  return hipGetLastError();
+}
+
+template <int BLOCK>
+hipError_t launch_fused_b(const Geometry &g, const State &s, int adjoint, float *model_out,
+                          hipStream_t st) {
+  switch (g.nd) {
+    case 5: return launch_fused_t<BLOCK, 5>(g, s, adjoint, model_out, st);
+    case 7: return launch_fused_t<BLOCK, 7>(g, s, adjoint, model_out, st);
+    case 9: return launch_fused_t<BLOCK, 9>(g, s, adjoint, model_out, st);
+    case 11: return launch_fused_t<BLOCK, 11>(g, s, adjoint, model_out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool fused_supported(int block, int nd) {
+  return (block == 128 || block == 256 || block == 512) &&
+         (nd == 5 || nd == 7 || nd == 9 || nd == 11);
+}
+
+size_t fused_smem_bytes(const Geometry &g) {
+  return (size_t)fused_layout(g, g.block / 64, 3 * g.nd - 1).bytes;
+}
+
+hipError_t launch_fused(const Geometry &g, const State &s, int adjoint, float *model_out,
+                        hipStream_t st) {
+  switch (g.block) {
+    case 128: return launch_fused_b<128>(g, s, adjoint, model_out, st);
+    case 256: return launch_fused_b<256>(g, s, adjoint, model_out, st);
+    case 512: return launch_fused_b<512>(g, s, adjoint, model_out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lasp

@@ -1,0 +1,199 @@
+// Once-per-fit preparation of each spectrum: pixel weights, the flux weight
+// w of Eq. 6 (a flux quantile, Section 3.3 "Setting spectral weighting
+// factors"), the lane-major (o/w, W w^2) layout read by the fused pass, and
+// the initial Adam state.
+#include "lasp_internal.h"
+
+namespace lasp {
+namespace {
+
+constexpr int kPrepBlock = 256;
+
+__device__ inline bool pixel_ok(float o, float iv) {
+  return isfinite(o) && isfinite(iv) && iv > 0.f;
+}
+
+// Order-preserving map of a float to an unsigned key.
+__device__ inline uint32_t fkey(float f) {
+  uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float funkey(uint32_t k) {
+  uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __uint_as_float(b);
+}
+
+// k-th smallest (0-based) flux among the valid pixels of one spectrum, by a
+// four-pass 8-bit radix select over the order-preserving keys.
+__device__ float block_select(const float *obs, const float *ivar, int P, uint32_t k,
+                              uint32_t *hist, uint32_t *sh) {
+  const int tid = threadIdx.x;
+  uint32_t prefix = 0, mask = 0;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += kPrepBlock) hist[i] = 0;
+    __syncthreads();
+    for (int j = tid; j < P; j += kPrepBlock) {
+      const float o = obs[j], iv = ivar[j];
+      if (pixel_ok(o, iv)) {
+        const uint32_t key = fkey(o);
+        if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t cum = 0;
+      int d = 0;
+      for (; d < 255; ++d) {
+        if (cum + hist[d] > k) break;
+        cum += hist[d];
+      }
+      sh[0] = (uint32_t)d;
+      sh[1] = k - cum;
+    }
+    __syncthreads();
+    prefix |= sh[0] << shift;
+    mask |= 255u << shift;
+    k = sh[1];
+    __syncthreads();
+  }
+  return funkey(prefix);
+}
+
+__global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, const float *obs,
+                                                        const float *ivar, const float *init,
+                                                        double blo0, double blo1, double blo2,
+                                                        double blo3, double blo4, double bhi0,
+                                                        double bhi1, double bhi2, double bhi3,
+                                                        double bhi4, float quantile,
+                                                        int init_state) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh[2];
+  __shared__ int red_n[kPrepBlock / 64];
+  __shared__ int red_bad[kPrepBlock / 64];
+  const int spec = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const size_t row = (size_t)spec * g.P;
+  const float *o_row = obs + row;
+  const float *i_row = ivar + row;
+
+  int n = 0, bad = 0;
+  for (int j = tid; j < g.P; j += kPrepBlock) {
+    const float o = o_row[j], iv = i_row[j];
+    n += pixel_ok(o, iv) ? 1 : 0;
+    bad |= (!isfinite(o) || !isfinite(iv)) ? 1 : 0;
+  }
+  n = wave_sum(n);
+  bad = wave_sum(bad);
+  if (lane == 0) {
+    red_n[wave] = n;
+    red_bad[wave] = bad;
+  }
+  __syncthreads();
+  int n_eff = 0, any_bad = 0;
+  for (int w = 0; w < kPrepBlock / 64; ++w) {
+    n_eff += red_n[w];
+    any_bad |= red_bad[w];
+  }
+
+  // Flux weight: the requested quantile (linear interpolation between order
+  // statistics), rounded to the nearest power of two so that o/w and W w^2
+  // are exact in floating point.  The objective does not depend on w.
+  float w = 1.f;
+  if (quantile > 0.f && n_eff > 0) {
+    const float pos = quantile * (float)(n_eff - 1);
+    const uint32_t k0 = (uint32_t)floorf(pos);
+    const float frac = pos - (float)k0;
+    const float v0 = block_select(o_row, i_row, g.P, k0, hist, sh);
+    float q = v0;
+    if (frac > 0.f && k0 + 1 < (uint32_t)n_eff) {
+      const float v1 = block_select(o_row, i_row, g.P, k0 + 1, hist, sh);
+      q = v0 + frac * (v1 - v0);
+    }
+    if (q > 0.f && isfinite(q)) w = exp2f(rintf(log2f(q)));
+    if (!(w > 0.f) || !isfinite(w) || !isfinite(1.f / (w * w))) w = 1.f;
+  }
+  const float inv_w = 1.f / w;
+  const float w2 = w * w;
+
+  // Lane-major layout for the fused pass: slot (i, lane) holds pixel
+  // lane * kNPL + i, so a lane reads its pixels with coalesced loads.
+  float2 *dst = s.ow + (size_t)spec * kNPL * g.block;
+  const int slots = kNPL * g.block;
+  for (int q = tid; q < slots; q += kPrepBlock) {
+    const int i = q / g.block, ln = q - i * g.block;
+    const int j = ln * kNPL + i;
+    float2 val = make_float2(0.f, 0.f);
+    if (j < g.P) {
+      const float o = o_row[j], iv = i_row[j];
+      if (pixel_ok(o, iv)) val = make_float2(o * inv_w, iv * w2);
+    }
+    dst[q] = val;
+  }
+
+  if (tid == 0) {
+    uint32_t st = 0;
+    if (any_bad) st |= kStNonfinite;
+    if (n_eff <= kNP + g.nd) st |= kStNoData;
+    s.status[spec] = st;
+    s.neff[spec] = n_eff;
+    s.wscale[spec] = w;
+    if (init_state) {
+      const double lo[5] = {blo0, blo1, blo2, blo3, blo4};
+      const double hi[5] = {bhi0, bhi1, bhi2, bhi3, bhi4};
+      for (int t = 0; t < kNP; ++t) {
+        double th = (double)init[(size_t)spec * kNP + t];
+        if (t == 0) th = log10(th);
+        s.u[(size_t)spec * kNP + t] = (float)(2.0 * (th - lo[t]) / (hi[t] - lo[t]) - 1.0);
+        s.m[(size_t)spec * kNP + t] = 0.f;
+        s.v[(size_t)spec * kNP + t] = 0.f;
+      }
+      s.t[spec] = 0;
+    }
+  }
+}
+
+// Physical parameters, status and chi2 at the end of a fit.
+__global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double blo2, double blo3,
+                           double blo4, double bhi0, double bhi1, double bhi2, double bhi3,
+                           double bhi4, float *out_params, uint32_t *status_out,
+                           double *chi2_out) {
+  const int spec = blockIdx.x * blockDim.x + threadIdx.x;
+  if (spec >= g.B) return;
+  const double lo[5] = {blo0, blo1, blo2, blo3, blo4};
+  const double hi[5] = {bhi0, bhi1, bhi2, bhi3, bhi4};
+  uint32_t st = s.status[spec];
+  for (int t = 0; t < kNP; ++t) {
+    const double u = (double)s.u[(size_t)spec * kNP + t];
+    if (!(fabs(u) <= 1.5)) st |= kStOutOfBox;
+    double th = lo[t] + 0.5 * (u + 1.0) * (hi[t] - lo[t]);
+    if (t == 0) th = exp10(th);
+    out_params[(size_t)spec * kNP + t] = (float)th;
+  }
+  s.status[spec] = st;
+  if (status_out) status_out[spec] = st;
+  if (chi2_out) chi2_out[spec] = s.chi2[spec];
+}
+
+}  // namespace
+
+hipError_t launch_prepare(const Geometry &g, const State &s, const float *obs, const float *ivar,
+                          const float *init_params, const double *lo, const double *hi,
+                          float weight_quantile, int init_state, hipStream_t st) {
+  hipLaunchKernelGGL(k_prepare, dim3(g.B), dim3(kPrepBlock), 0, st, g, s, obs, ivar, init_params,
+                     lo[0], lo[1], lo[2], lo[3], lo[4], hi[0], hi[1], hi[2], hi[3], hi[4],
+                     weight_quantile, init_state);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Geometry &g, const State &s, const double *lo, const double *hi,
+                           float *out_params, uint32_t *status_out, double *chi2_out,
+                           hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_finalize, dim3((g.B + bs - 1) / bs), dim3(bs), 0, st, g, s, lo[0], lo[1],
+                     lo[2], lo[3], lo[4], hi[0], hi[1], hi[2], hi[3], hi[4], out_params,
+                     status_out, chi2_out);
+  return hipGetLastError();
+}
+
+}  // namespace lasp

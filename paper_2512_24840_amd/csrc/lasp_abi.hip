@@ -1,0 +1,353 @@
+// C ABI (include/lasp.h): argument validation, cached device scratch and the
+// launch sequence of a grouped fit.  Every number is computed by the device
+// kernels; this file only checks shapes and enqueues work.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "lasp.h"
+#include "lasp_internal.h"
+
+namespace {
+
+using lasp::Geometry;
+using lasp::State;
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int dev_fail(hipError_t e, const char *where) {
+  return fail(LASP_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Device scratch of one (device, stream) pair, grown on demand.
+struct Workspace {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0;
+  State s{};
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, void *>, Workspace *> g_ws;
+
+template <typename T>
+hipError_t grow(T *&p, size_t &cap, size_t need) {
+  if (need <= cap && p != nullptr) return hipSuccess;
+  if (p) {
+    hipError_t e = hipFree(p);
+    if (e != hipSuccess) return e;
+    p = nullptr;
+    cap = 0;
+  }
+  hipError_t e = hipMalloc((void **)&p, need * sizeof(T) + 256);
+  if (e == hipSuccess) cap = need;
+  return e;
+}
+
+void free_ws(Workspace *w) {
+  State &s = w->s;
+  void *ptrs[] = {s.u, s.m, s.v, s.t, s.ow, s.wscale, s.neff, s.status, s.fp, s.fbar, s.g45, s.chi2,
+                  s.basis, s.basis_hi, s.basis_lo};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  w->s = State{};
+  w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = 0;
+}
+
+int get_workspace(const Geometry &g, int fp_rows, hipStream_t st, Workspace **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, (void *)st);
+  Workspace *w = g_ws[key];
+  if (!w) {
+    w = new Workspace();
+    w->device = dev;
+    w->stream = st;
+    g_ws[key] = w;
+  }
+  const size_t B = (size_t)g.B;
+  const size_t need_ow = B * lasp::kNPL * g.block;
+  const size_t need_fp = B * fp_rows * g.ldF;
+  const size_t need_fbar = B * g.ldF;
+  const size_t need_basis = (size_t)lasp::kNB * g.ldF;
+  const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
+                      need_fbar > w->cap_fbar || need_basis > w->cap_basis || !w->s.u;
+  if (regrow) {
+    // earlier work on this stream may still use the old buffers
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+    State &s = w->s;
+    size_t cb = w->cap_B;
+    size_t c1 = cb, c2 = cb, c3 = cb, c4 = cb, c5 = cb, c6 = cb, c7 = cb, c8 = cb, c9 = cb;
+    hipError_t r = hipSuccess;
+    if (B > cb || !s.u) {
+      r = grow(s.u, c1, B * lasp::kNP);
+      if (r == hipSuccess) r = grow(s.m, c2, B * lasp::kNP);
+      if (r == hipSuccess) r = grow(s.v, c3, B * lasp::kNP);
+      if (r == hipSuccess) r = grow(s.t, c4, B);
+      if (r == hipSuccess) r = grow(s.wscale, c5, B);
+      if (r == hipSuccess) r = grow(s.neff, c6, B);
+      if (r == hipSuccess) r = grow(s.status, c7, B);
+      if (r == hipSuccess) r = grow(s.g45, c8, B * 2);
+      if (r == hipSuccess) r = grow(s.chi2, c9, B);
+      if (r == hipSuccess) w->cap_B = B;
+    }
+    if (r == hipSuccess) r = grow(s.ow, w->cap_ow, need_ow);
+    if (r == hipSuccess) r = grow(s.fp, w->cap_fp, need_fp);
+    if (r == hipSuccess) r = grow(s.fbar, w->cap_fbar, need_fbar);
+    if (r == hipSuccess) {
+      size_t cap = w->cap_basis;
+      r = grow(s.basis, cap, need_basis);
+      size_t cap2 = w->cap_basis, cap3 = w->cap_basis;
+      if (r == hipSuccess) r = grow(s.basis_hi, cap2, need_basis);
+      if (r == hipSuccess) r = grow(s.basis_lo, cap3, need_basis);
+      if (r == hipSuccess) w->cap_basis = need_basis;
+    }
+    if (r != hipSuccess) {
+      free_ws(w);
+      (void)hipGetLastError();
+      return fail(r == hipErrorOutOfMemory ? LASP_E_NOMEM : LASP_E_DEVICE,
+                  std::string("device allocation: ") + hipGetErrorString(r));
+    }
+  }
+  *out = w;
+  return LASP_OK;
+}
+
+// Validates options and the wavelength grid and fills the geometry.
+int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
+  if (!o) return fail(LASP_E_ARG, "opts is NULL");
+  if (o->n_spec < 0) return fail(LASP_E_ARG, "n_spec < 0");
+  if (o->n_pix < 32) return fail(LASP_E_ARG, "n_pix must be >= 32");
+  if (o->n_basis != LASP_N_BASIS) return fail(LASP_E_ARG, "n_basis must be 20");
+  if (o->margin < 1 || o->margin > 80) return fail(LASP_E_ARG, "margin must be in [1, 80]");
+  if (!(o->degree == 4 || o->degree == 6 || o->degree == 8 || o->degree == 10))
+    return fail(LASP_E_UNSUPPORTED, "degree must be one of 4, 6, 8, 10");
+  if (o->precision != LASP_PREC_FP32)
+    return fail(LASP_E_UNSUPPORTED, "only LASP_PREC_FP32 is available in this build");
+  for (int t = 0; t < LASP_N_PAR; ++t)
+    if (!(o->box_hi[t] > o->box_lo[t]) || !isfinite(o->box_lo[t]) || !isfinite(o->box_hi[t]))
+      return fail(LASP_E_ARG, "box_hi must exceed box_lo (finite)");
+  if (!(o->lr > 0.f) || !(o->beta1 >= 0.f && o->beta1 < 1.f) || !(o->beta2 >= 0.f && o->beta2 < 1.f) ||
+      !(o->eps > 0.f))
+    return fail(LASP_E_ARG, "invalid Adam hyper-parameters");
+  if (o->n_arms < 0 || o->n_arms > LASP_MAX_ARMS) return fail(LASP_E_ARG, "n_arms must be 0..4");
+  if (!wave_grid) return fail(LASP_E_ARG, "wave_grid is NULL");
+
+  const int P = o->n_pix;
+  for (int j = 0; j < P; ++j)
+    if (!(wave_grid[j] > 0.0) || !isfinite(wave_grid[j]))
+      return fail(LASP_E_GRID, "wave_grid must be positive and finite");
+  const double dl = log10(wave_grid[P - 1] / wave_grid[0]) / (double)(P - 1);
+  if (!(dl > 0.0)) return fail(LASP_E_GRID, "wave_grid must increase");
+  for (int j = 0; j + 1 < P; ++j) {
+    const double st = log10(wave_grid[j + 1] / wave_grid[j]);
+    if (fabs(st - dl) > 1e-6 * dl) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "wave_grid not uniform in log10 at pixel %d (step %.9g vs %.9g)", j,
+               st, dl);
+      return fail(LASP_E_GRID, buf);
+    }
+  }
+
+  memset(g, 0, sizeof(*g));
+  g->B = o->n_spec;
+  g->P = P;
+  g->M = o->margin;
+  g->Pe = P + 2 * o->margin;
+  g->ldF = (g->Pe + 63) & ~63;
+  g->nd = o->degree + 1;
+  g->block = 0;
+  for (int b : {128, 256, 512})
+    if (lasp::kNPL * b >= g->ldF) {
+      g->block = b;
+      break;
+    }
+  if (!g->block) return fail(LASP_E_UNSUPPORTED, "n_pix + 2*margin exceeds 8704");
+  if (o->n_arms == 0) {
+    g->n_arms = 1;
+    g->bare = 1;
+    g->arm_start[0] = 0;
+    g->arm_start[1] = P;
+  } else {
+    g->n_arms = o->n_arms;
+    g->bare = 0;
+    if (o->arm_start[0] != 0) return fail(LASP_E_ARG, "arm_start[0] must be 0");
+    for (int a = 0; a < o->n_arms; ++a) {
+      if (a > 0 && o->arm_start[a] <= o->arm_start[a - 1])
+        return fail(LASP_E_ARG, "arm_start must increase");
+      if (o->arm_start[a] >= P) return fail(LASP_E_ARG, "arm_start beyond n_pix");
+      if (!(o->arm_sigma_kms[a] >= 0.f) || !isfinite(o->arm_sigma_kms[a]))
+        return fail(LASP_E_ARG, "arm_sigma_kms must be finite and >= 0");
+      g->arm_start[a] = o->arm_start[a];
+      g->arm_sig2[a] = o->arm_sigma_kms[a] * o->arm_sigma_kms[a];
+    }
+    g->arm_start[o->n_arms] = P;
+  }
+  g->inv_scale = (float)(1.0 / (lasp::kCkms * lasp::kLn10 * dl));
+  g->rv_lo = (float)o->box_lo[3];
+  g->rv_half = (float)(0.5 * (o->box_hi[3] - o->box_lo[3]));
+  g->sg_lo = (float)o->box_lo[4];
+  g->sg_half = (float)(0.5 * (o->box_hi[4] - o->box_lo[4]));
+  if (lasp::fused_smem_bytes(*g) > 160 * 1024)
+    return fail(LASP_E_UNSUPPORTED, "shape needs more LDS than a workgroup has");
+  return LASP_OK;
+}
+
+// Copies the caller's basis into the zero-padded [20][ldF] layout.
+__global__ void k_copy_basis(const float *src, float *dst, int Pe, int ldF) {
+  const int k = blockIdx.y;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ldF; c += gridDim.x * blockDim.x)
+    dst[(size_t)k * ldF + c] = c < Pe ? src[(size_t)k * Pe + c] : 0.f;
+}
+
+int copy_basis(const Geometry &g, const State &s, const float *basis, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_basis, dim3((g.ldF + 255) / 256, lasp::kNB), dim3(256), 0, st, basis,
+                     s.basis, g.Pe, g.ldF);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LASP_OK : dev_fail(e, "copy basis");
+}
+
+#define LASP_CHECK(call, what)                 \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) return dev_fail(e_, what); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+void lasp_default_opts(lasp_opts *o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->n_basis = LASP_N_BASIS;
+  o->margin = 64;
+  o->degree = 10;
+  o->precision = LASP_PREC_FP32;
+  const double lo[5] = {log10(4000.0), 1.0, -2.5, -300.0, 50.0};
+  const double hi[5] = {log10(8000.0), 5.0, 0.5, 300.0, 150.0};
+  for (int t = 0; t < 5; ++t) {
+    o->box_lo[t] = lo[t];
+    o->box_hi[t] = hi[t];
+  }
+  o->lr = 1e-2f;
+  o->beta1 = 0.9f;
+  o->beta2 = 0.999f;
+  o->eps = 1e-8f;
+  o->weight_quantile = 0.5f;
+}
+
+const char *lasp_last_error(void) { return g_err.c_str(); }
+
+void lasp_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto &kv : g_ws) {
+    Workspace *w = kv.second;
+    (void)hipSetDevice(w->device);
+    (void)hipStreamSynchronize(w->stream);
+    free_ws(w);
+    delete w;
+  }
+  g_ws.clear();
+  (void)hipSetDevice(cur);
+}
+
+int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid, const float *basis,
+                   const float *init_params, float *out_params, double *out_cov, int32_t n_steps,
+                   const lasp_opts *opts) {
+  g_err.clear();
+  Geometry g;
+  int rc = make_geometry(opts, wave_grid, &g);
+  if (rc) return rc;
+  if (!obs || !ivar || !basis || !init_params || !out_params)
+    return fail(LASP_E_ARG, "obs, ivar, basis, init_params and out_params are required");
+  if (n_steps < 0) return fail(LASP_E_ARG, "n_steps < 0");
+  if (g.B == 0) return LASP_OK;
+  hipStream_t st = (hipStream_t)opts->stream;
+  Workspace *w = nullptr;
+  rc = get_workspace(g, out_cov ? 4 : 1, st, &w);
+  if (rc) return rc;
+  State s = w->s;
+  rc = copy_basis(g, s, basis, st);
+  if (rc) return rc;
+  LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, init_params, opts->box_lo, opts->box_hi,
+                                  opts->weight_quantile, 1, st),
+             "prepare");
+  const lasp::AdamCfg adam{opts->lr, opts->beta1, opts->beta2, opts->eps};
+  s.fp_stride = g.ldF;
+  for (int it = 0; it < n_steps; ++it) {
+    LASP_CHECK(lasp::launch_interp_fwd(g, s, 0, 0, st), "interpolator contraction");
+    LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, st), "fused pass");
+    LASP_CHECK(lasp::launch_interp_bwd(g, s, &adam, nullptr, st), "adjoint contraction + Adam");
+  }
+  // chi2 and status at the returned parameters; derivative rows for the covariance
+  s.fp_stride = out_cov ? 4 * g.ldF : g.ldF;
+  LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, 0, st), "interpolator contraction");
+  LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, st), "fused pass");
+  if (out_cov)
+    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, nullptr, st),
+               "covariance");
+  LASP_CHECK(lasp::launch_finalize(g, s, opts->box_lo, opts->box_hi, out_params, opts->status,
+                                   opts->out_chi2, st),
+             "finalize");
+  return LASP_OK;
+}
+
+int lasp_forward(const float *obs, const float *ivar, const double *wave_grid, const float *basis,
+                 const float *u, float *out_model, double *out_chi2, int32_t *out_neff,
+                 float *out_grad, float *out_jac, const lasp_opts *opts) {
+  g_err.clear();
+  Geometry g;
+  int rc = make_geometry(opts, wave_grid, &g);
+  if (rc) return rc;
+  if (!obs || !ivar || !basis || !u || !out_chi2)
+    return fail(LASP_E_ARG, "obs, ivar, basis, u and out_chi2 are required");
+  if (g.B == 0) return LASP_OK;
+  hipStream_t st = (hipStream_t)opts->stream;
+  Workspace *w = nullptr;
+  rc = get_workspace(g, out_jac ? 4 : 1, st, &w);
+  if (rc) return rc;
+  State s = w->s;
+  rc = copy_basis(g, s, basis, st);
+  if (rc) return rc;
+  LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, nullptr, opts->box_lo, opts->box_hi,
+                                  opts->weight_quantile, 0, st),
+             "prepare");
+  LASP_CHECK(hipMemcpyAsync(s.u, u, sizeof(float) * lasp::kNP * g.B, hipMemcpyDeviceToDevice, st),
+             "copy u");
+  s.fp_stride = out_jac ? 4 * g.ldF : g.ldF;
+  LASP_CHECK(lasp::launch_interp_fwd(g, s, out_jac ? 1 : 0, 0, st), "interpolator contraction");
+  LASP_CHECK(lasp::launch_fused(g, s, out_grad ? 1 : 0, out_model, st), "fused pass");
+  if (out_grad)
+    LASP_CHECK(lasp::launch_interp_bwd(g, s, nullptr, out_grad, st), "adjoint contraction");
+  if (out_jac)
+    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, nullptr, out_jac, st),
+               "model Jacobian");
+  LASP_CHECK(hipMemcpyAsync(out_chi2, s.chi2, sizeof(double) * g.B, hipMemcpyDeviceToDevice, st),
+             "copy chi2");
+  if (out_neff)
+    LASP_CHECK(hipMemcpyAsync(out_neff, s.neff, sizeof(int) * g.B, hipMemcpyDeviceToDevice, st),
+               "copy n_eff");
+  if (opts->status)
+    LASP_CHECK(hipMemcpyAsync(opts->status, s.status, sizeof(uint32_t) * g.B,
+                              hipMemcpyDeviceToDevice, st),
+               "copy status");
+  return LASP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Internal declarations of the HIP library: argument blocks, device helpers
+// and kernel launchers.  Not part of the public ABI (include/lasp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lasp {
+
+constexpr double kCkms = 299792.458;            // speed of light, km/s
+constexpr double kLn10 = 2.302585092994045684;  // ln 10
+constexpr float kSigmaFloorPx = 0.1f;           // lower bound of the kernel width, pixels
+constexpr int kNB = 20;                         // interpolator terms (cubic in 3 coordinates)
+constexpr int kNP = 5;                          // free parameters per spectrum
+constexpr int kNPL = 17;                        // pixels owned by one lane in the fused pass
+constexpr int kTB = 8;                          // taps per register block
+constexpr int kMaxArms = 4;
+
+// Status bits (same values as LASP_ST_* in lasp.h).
+constexpr uint32_t kStNonfinite = 0x01u;
+constexpr uint32_t kStNoData = 0x02u;
+constexpr uint32_t kStSingular = 0x04u;
+constexpr uint32_t kStContNonpos = 0x08u;
+constexpr uint32_t kStOutOfBox = 0x10u;
+constexpr uint32_t kStSigmaFloor = 0x20u;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Geometry shared by every per-step kernel.
+struct Geometry {
+  int B;        // spectra
+  int P;        // pixels
+  int M;        // margin
+  int Pe;       // P + 2M basis columns
+  int ldF;      // row stride of F' / F-bar' / padded basis (multiple of 64, >= Pe)
+  int nd;       // continuum coefficients D + 1
+  int block;    // threads of the fused pass
+  int n_arms;   // >= 1
+  int arm_start[kMaxArms + 1];  // arm a covers pixels [arm_start[a], arm_start[a+1])
+  float arm_sig2[kMaxArms];     // instrumental sigma^2, (km/s)^2 (0 for a single bare arm)
+  int bare;                     // 1: one arm without instrument term
+  float inv_scale;              // pixels per km/s = 1 / (c ln10 dlog10)
+  float rv_lo, rv_half;         // RV = rv_lo + (u4 + 1) rv_half
+  float sg_lo, sg_half;         // sigma = sg_lo + (u5 + 1) sg_half
+};
+
+// Per-spectrum state and scratch owned by the library.
+struct State {
+  float *u;         // [B][5] normalised parameters
+  float *m;         // [B][5] Adam first moment
+  float *v;         // [B][5] Adam second moment
+  int *t;           // [B] Adam step count
+  float2 *ow;       // [B][kNPL][block] (o/w, W w^2) in lane-major order
+  float *wscale;    // [B] flux weight w
+  int *neff;        // [B]
+  uint32_t *status; // [B]
+  float *fp;        // [B][ldF] (or [B][4][ldF]) F'
+  int fp_stride;    // floats between consecutive spectra in fp (ldF or 4 ldF)
+  float *fbar;      // [B][ldF] F-bar'
+  float *g45;       // [B][2] dJ/du4, dJ/du5
+  double *chi2;     // [B]
+  float *basis;     // [20][ldF] zero-padded copy of the basis
+  uint16_t *basis_hi;  // [20][ldF] bf16 high part (BF16x3)
+  uint16_t *basis_lo;  // [20][ldF] bf16 low part (BF16x3)
+};
+
+struct AdamCfg {
+  float lr, beta1, beta2, eps;
+};
+
+// ---------------------------------------------------------------- host side
+hipError_t launch_prepare(const Geometry &g, const State &s, const float *obs, const float *ivar,
+                          const float *init_params, const double *box_lo, const double *box_hi,
+                          float weight_quantile, int init_state, hipStream_t st);
+hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, int bf16x3,
+                             hipStream_t st);
+hipError_t launch_fused(const Geometry &g, const State &s, int adjoint, float *model_out,
+                        hipStream_t st);
+hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *adam,
+                             float *grad_out, hipStream_t st);
+hipError_t launch_finalize(const Geometry &g, const State &s, const double *box_lo,
+                           const double *box_hi, float *out_params, uint32_t *status_out,
+                           double *chi2_out, hipStream_t st);
+hipError_t launch_cov(const Geometry &g, const State &s, const double *box_lo, const double *box_hi,
+                      double *out_cov, float *out_jac, hipStream_t st);
+bool fused_supported(int block, int nd);
+size_t fused_smem_bytes(const Geometry &g);
+
+// -------------------------------------------------------------- device side
+#ifdef __HIPCC__
+
+// Eq. 1 features: monomials of total degree <= 3 in x = (u1, u2, u3),
+// graded lexicographic order.
+__device__ inline void features(float x, float y, float z, float *phi) {
+  phi[0] = 1.f;
+  phi[1] = x; phi[2] = y; phi[3] = z;
+  phi[4] = x * x; phi[5] = x * y; phi[6] = x * z; phi[7] = y * y; phi[8] = y * z; phi[9] = z * z;
+  phi[10] = x * x * x; phi[11] = x * x * y; phi[12] = x * x * z; phi[13] = x * y * y;
+  phi[14] = x * y * z; phi[15] = x * z * z; phi[16] = y * y * y; phi[17] = y * y * z;
+  phi[18] = y * z * z; phi[19] = z * z * z;
+}
+
+// d phi_k / d x_t for t = 0, 1, 2 (d[t][k]).
+__device__ inline void feature_derivs(float x, float y, float z, float (*d)[kNB]) {
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) d[t][k] = 0.f;
+  d[0][1] = 1.f; d[1][2] = 1.f; d[2][3] = 1.f;
+  d[0][4] = 2.f * x;
+  d[0][5] = y; d[1][5] = x;
+  d[0][6] = z; d[2][6] = x;
+  d[1][7] = 2.f * y;
+  d[1][8] = z; d[2][8] = y;
+  d[2][9] = 2.f * z;
+  d[0][10] = 3.f * x * x;
+  d[0][11] = 2.f * x * y; d[1][11] = x * x;
+  d[0][12] = 2.f * x * z; d[2][12] = x * x;
+  d[0][13] = y * y; d[1][13] = 2.f * x * y;
+  d[0][14] = y * z; d[1][14] = x * z; d[2][14] = x * y;
+  d[0][15] = z * z; d[2][15] = 2.f * x * z;
+  d[1][16] = 3.f * y * y;
+  d[1][17] = 2.f * y * z; d[2][17] = y * y;
+  d[1][18] = z * z; d[2][18] = 2.f * y * z;
+  d[2][19] = 3.f * z * z;
+}
+
+// Butterfly reduce-scatter of N per-lane values over a 64-lane wave.
+// On return every lane holds, in v[0], the wave-wide sum of value index
+// lane / (64 / N); lanes with lane % (64 / N) == 0 are the writers.
+template <int N, typename T>
+__device__ inline T wave_reduce_scatter(T (&v)[N], int lane) {
+  static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
+  int off = 32;
+#pragma unroll
+  for (int cnt = N; cnt > 1; cnt >>= 1, off >>= 1) {
+    const int half = cnt >> 1;
+    const bool hi = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      T send = hi ? v[i] : v[half + i];
+      T keep = hi ? v[half + i] : v[i];
+      v[i] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  T r = v[0];
+  for (; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
+  return r;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ inline float wave_min(float x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+template <int N>
+struct Pow2 {
+  static constexpr int v = N <= 1 ? 1 : 2 * Pow2<(N + 1) / 2>::v;
+};
+template <>
+struct Pow2<1> {
+  static constexpr int v = 1;
+};
+
+// Sum of NV per-lane doubles over the workgroup, result in out[0..NV).
+// Chunks of 32 go through the wave butterfly, then across waves in a
+// fixed order (deterministic).
+template <int NW, int NV>
+__device__ inline void block_sum_doubles(const double (&acc)[NV], double *red, double *out,
+                                         int lane, int wave) {
+  constexpr int kChunks = (NV + 31) / 32;
+#pragma unroll
+  for (int ch = 0; ch < kChunks; ++ch) {
+    constexpr int kW = NV < 32 ? Pow2<NV>::v : 32;
+    double tmp[kW];
+#pragma unroll
+    for (int i = 0; i < kW; ++i) tmp[i] = (ch * 32 + i < NV) ? acc[(ch * 32 + i) % NV] : 0.0;
+    const double r = wave_reduce_scatter<kW, double>(tmp, lane);
+    constexpr int kStride = 64 / kW;
+    if ((lane % kStride) == 0) red[wave * 64 + lane / kStride] = r;
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < kW && ch * 32 + t < NV) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += red[w * 64 + t];
+      out[ch * 32 + t] = s;
+    }
+    __syncthreads();
+  }
+}
+
+#endif  // __HIPCC__
+
+}  // namespace lasp

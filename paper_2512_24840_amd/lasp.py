@@ -1,0 +1,229 @@
+"""ctypes binding of liblasp.so (include/lasp.h): argument marshalling only.
+
+Every step of the fit runs in the HIP kernels behind the C ABI; this module
+checks tensor shapes, dtypes and devices, fills ``lasp_opts`` and forwards
+device pointers and the current HIP stream.  It raises if the library has
+not been built -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblasp.so")
+
+LASP_OK = 0
+ERRORS = {-1: "LASP_E_ARG", -2: "LASP_E_GRID", -3: "LASP_E_DEVICE", -4: "LASP_E_NOMEM",
+          -5: "LASP_E_UNSUPPORTED"}
+ST_NONFINITE_INPUT = 0x01
+ST_NO_DATA = 0x02
+ST_SINGULAR = 0x04
+ST_CONT_NONPOS = 0x08
+ST_OUT_OF_BOX = 0x10
+ST_SIGMA_FLOOR = 0x20
+PREC = {"fp32": 0, "bf16x3": 1}
+N_BASIS = 20
+N_PAR = 5
+EXPORTED = ("lasp_default_opts", "lasp_fit_group", "lasp_forward", "lasp_last_error",
+            "lasp_release")
+
+
+class LaspError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+        self.code = code
+
+
+class LaspOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_spec", ctypes.c_int32),
+        ("n_pix", ctypes.c_int32),
+        ("n_basis", ctypes.c_int32),
+        ("margin", ctypes.c_int32),
+        ("degree", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("box_lo", ctypes.c_double * 5),
+        ("box_hi", ctypes.c_double * 5),
+        ("lr", ctypes.c_float),
+        ("beta1", ctypes.c_float),
+        ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("weight_quantile", ctypes.c_float),
+        ("n_arms", ctypes.c_int32),
+        ("arm_start", ctypes.c_int32 * 4),
+        ("arm_sigma_kms", ctypes.c_float * 4),
+        ("stream", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("out_chi2", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load() -> ctypes.CDLL:
+    """Load liblasp.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(_LIB_PATH)
+        vp = ctypes.c_void_p
+        lib.lasp_default_opts.argtypes = [ctypes.POINTER(LaspOpts)]
+        lib.lasp_default_opts.restype = None
+        lib.lasp_fit_group.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32,
+                                       ctypes.POINTER(LaspOpts)]
+        lib.lasp_fit_group.restype = ctypes.c_int
+        lib.lasp_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                     ctypes.POINTER(LaspOpts)]
+        lib.lasp_forward.restype = ctypes.c_int
+        lib.lasp_last_error.argtypes = []
+        lib.lasp_last_error.restype = ctypes.c_char_p
+        lib.lasp_release.argtypes = []
+        lib.lasp_release.restype = None
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != LASP_OK:
+        raise LaspError(rc, load().lasp_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, name: str, dtype, shape):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+@dataclasses.dataclass
+class Arms:
+    start: tuple
+    sigma_kms: tuple
+
+
+def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
+              betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5, arms: Arms | None = None,
+              box=None, stream=None) -> LaspOpts:
+    o = LaspOpts()
+    load().lasp_default_opts(ctypes.byref(o))
+    o.n_spec, o.n_pix, o.margin, o.degree = int(n_spec), int(n_pix), int(margin), int(degree)
+    o.precision = PREC[precision]
+    o.lr, o.beta1, o.beta2, o.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
+    o.weight_quantile = float(weight_quantile)
+    if box is not None:
+        lo, hi = box
+        for t in range(5):
+            o.box_lo[t], o.box_hi[t] = float(lo[t]), float(hi[t])
+    if arms is not None and len(arms.start) > 0:
+        o.n_arms = len(arms.start)
+        for a, (s, g) in enumerate(zip(arms.start, arms.sigma_kms)):
+            o.arm_start[a], o.arm_sigma_kms[a] = int(s), float(g)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o.stream = ctypes.c_void_p(stream.cuda_stream)
+    return o
+
+
+def _grid(wave_grid, n_pix):
+    g = np.ascontiguousarray(np.asarray(wave_grid, dtype=np.float64))
+    if g.shape != (n_pix,):
+        raise ValueError(f"wave_grid must have shape ({n_pix},)")
+    return g
+
+
+@dataclasses.dataclass
+class FitResult:
+    params: torch.Tensor          # [B, 5] float32, physical units
+    cov: torch.Tensor | None      # [B, 5, 5] float64, physical units
+    status: torch.Tensor          # [B] int32 (LASP_ST_* bits)
+    chi2: torch.Tensor            # [B] float64
+
+
+def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=False,
+              margin=64, degree=10, precision="fp32", lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
+              weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
+              out: FitResult | None = None) -> FitResult:
+    """lasp_fit_group on device tensors; returns after enqueueing (stream ordered)."""
+    lib = load()
+    B, P = obs.shape
+    _dev(obs, "obs", torch.float32, (B, P))
+    _dev(ivar, "ivar", torch.float32, (B, P))
+    _dev(basis, "basis", torch.float32, (N_BASIS, P + 2 * margin))
+    _dev(init_params, "init_params", torch.float32, (B, N_PAR))
+    grid = _grid(wave_grid, P)
+    dev = obs.device
+    if out is None:
+        out = FitResult(torch.empty((B, N_PAR), dtype=torch.float32, device=dev),
+                        torch.empty((B, N_PAR, N_PAR), dtype=torch.float64, device=dev)
+                        if want_cov else None,
+                        torch.empty(B, dtype=torch.int32, device=dev),
+                        torch.empty(B, dtype=torch.float64, device=dev))
+    o = make_opts(B, P, margin=margin, degree=degree, precision=precision, lr=lr, betas=betas,
+                  eps=eps, weight_quantile=weight_quantile, arms=arms, box=box, stream=stream)
+    o.status = ctypes.c_void_p(out.status.data_ptr())
+    o.out_chi2 = ctypes.c_void_p(out.chi2.data_ptr())
+    with torch.cuda.device(dev):
+        rc = lib.lasp_fit_group(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
+                                _ptr(basis), _ptr(init_params), _ptr(out.params), _ptr(out.cov),
+                                int(n_steps), ctypes.byref(o))
+    _check(rc)
+    return out
+
+
+def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False,
+            want_jac=False, margin=64, degree=10, precision="fp32", weight_quantile=0.5,
+            arms: Arms | None = None, box=None, stream=None) -> dict:
+    """lasp_forward: model, chi2, n_eff, gradient and model Jacobian at fixed u."""
+    lib = load()
+    B, P = obs.shape
+    _dev(obs, "obs", torch.float32, (B, P))
+    _dev(ivar, "ivar", torch.float32, (B, P))
+    _dev(basis, "basis", torch.float32, (N_BASIS, P + 2 * margin))
+    _dev(u, "u", torch.float32, (B, N_PAR))
+    grid = _grid(wave_grid, P)
+    dev = obs.device
+    res = dict(chi2=torch.empty(B, dtype=torch.float64, device=dev),
+               n_eff=torch.empty(B, dtype=torch.int32, device=dev),
+               status=torch.empty(B, dtype=torch.int32, device=dev))
+    res["model"] = torch.empty((B, P), dtype=torch.float32, device=dev) if want_model else None
+    res["grad"] = torch.empty((B, N_PAR), dtype=torch.float32, device=dev) if want_grad else None
+    res["jac"] = torch.empty((B, N_PAR, P), dtype=torch.float32, device=dev) if want_jac else None
+    o = make_opts(B, P, margin=margin, degree=degree, precision=precision,
+                  weight_quantile=weight_quantile, arms=arms, box=box, stream=stream)
+    o.status = ctypes.c_void_p(res["status"].data_ptr())
+    with torch.cuda.device(dev):
+        rc = lib.lasp_forward(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
+                              _ptr(basis), _ptr(u), _ptr(res["model"]), _ptr(res["chi2"]),
+                              _ptr(res["n_eff"]), _ptr(res["grad"]), _ptr(res["jac"]),
+                              ctypes.byref(o))
+    _check(rc)
+    return res
+
+
+def release():
+    load().lasp_release()
+
+
+DEFAULT_BOX = (np.array([math.log10(4000.0), 1.0, -2.5, -300.0, 50.0]),
+               np.array([math.log10(8000.0), 5.0, 0.5, 300.0, 150.0]))
