@@ -34,6 +34,7 @@
 #ifndef LASP_H
 #define LASP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -134,16 +135,75 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
  * Model at fixed normalised parameters (one forward pass and its adjoint).
  *   u         [B][5] float normalised parameters
  *   out_model [B][P] float  C (.) F'' in the units of obs, or NULL
- *   out_chi2  [B] double    chi2 (required)
+ *   out_chi2  [B] double    chi2 = sum_j W_j (o_j - C_j F''_j)^2 (required)
+ *   out_J     [B] float     objective J = chi2 / n_eff (0 when n_eff = 0), or NULL
  *   out_neff  [B] int32     pixels with positive weight, or NULL
- *   out_grad  [B][5] float  d(chi2/n_eff)/du with the continuum held at its
- *             least-squares value (envelope theorem), or NULL
+ *   out_grad  [B][5] float  dJ/du with the continuum held at its least-squares
+ *             value (envelope theorem), or NULL
  *   out_jac   [B][5][P] float d model / d u at fixed continuum, or NULL
+ *   out_cov   [B][5][5] double covariance at u in physical units
+ *             (Section 2.2 stage 9), or NULL
  * Other arguments as in lasp_fit_group (opts->out_chi2 is ignored).
  */
 int lasp_forward(const float *obs, const float *ivar, const double *wave_grid,
                  const float *basis, const float *u, float *out_model, double *out_chi2,
-                 int32_t *out_neff, float *out_grad, float *out_jac, const lasp_opts *opts);
+                 float *out_J, int32_t *out_neff, float *out_grad, float *out_jac,
+                 double *out_cov, const lasp_opts *opts);
+
+/*
+ * Kernel timing for benchmarks.  lasp_profile_enable(mask) clears the
+ * counters and, for every kernel class whose bit (1 << LASP_K_*) is set in
+ * mask, brackets each later launch with a pair of hipEvents recorded on the
+ * launch's stream (mask 0 switches timing off).  lasp_profile_read waits for
+ * the recorded events and returns, per class, the summed kernel time in ms
+ * and the number of launches (arrays of n <= LASP_NK entries, host memory).
+ * Timing adds two event records per bracketed launch.  Not thread safe:
+ * use from one host thread.
+ */
+#define LASP_K_PREPARE 0
+#define LASP_K_INTERP_FWD 1
+#define LASP_K_FUSED 2
+#define LASP_K_INTERP_BWD 3
+#define LASP_K_COV 4
+#define LASP_K_FINALIZE 5
+#define LASP_NK 6
+int lasp_profile_enable(uint32_t mask);
+int lasp_profile_read(double *total_ms, int64_t *launches, int32_t n);
+
+/*
+ * Resident slot pools for continuous batching (serving).  A pool holds up to
+ * opts->n_spec fits of one spectral shape (opts: n_pix, margin, degree, arms,
+ * precision, box, Adam settings; the grid and basis are copied at creation)
+ * on the current device, with per-slot Adam state (u, m, v, step count) kept
+ * in device memory between calls.  All work is enqueued on opts->stream.
+ *   lasp_pool_slot_bytes  device bytes one slot occupies (for admission by
+ *                         memory footprint); 0 if opts are invalid.
+ *   lasp_pool_create      allocates the pool (LASP_E_NOMEM if it does not fit).
+ *   lasp_pool_load        prepares `count` spectra (obs, ivar [count][P],
+ *                         init_params [count][5], device) into slots
+ *                         [slot0, slot0 + count) and sets their step target
+ *                         to n_steps; their step counts restart at 0.
+ *   lasp_pool_step        advances every slot in [0, slot_end) whose step
+ *                         count is below its target by up to k Adam steps
+ *                         (Section 2.2 stages 2-8); other slots are untouched.
+ *   lasp_pool_finish      evaluates slots [slot0, slot0 + count) at their
+ *                         current parameters and writes out_params [count][5]
+ *                         (physical units), optional out_cov [count][5][5],
+ *                         status [count] and chi2 [count] (device).
+ *   lasp_pool_destroy     waits for the pool's stream and frees it.
+ * Slots are independent: a fit's result does not depend on which other
+ * slots are occupied.  Calls on one pool must come from one host thread.
+ */
+typedef struct lasp_pool lasp_pool;
+size_t lasp_pool_slot_bytes(const lasp_opts *opts, const double *wave_grid);
+int lasp_pool_create(const double *wave_grid, const float *basis, const lasp_opts *opts,
+                     lasp_pool **out);
+int lasp_pool_load(lasp_pool *pool, int32_t slot0, int32_t count, const float *obs,
+                   const float *ivar, const float *init_params, int32_t n_steps);
+int lasp_pool_step(lasp_pool *pool, int32_t slot_end, int32_t k);
+int lasp_pool_finish(lasp_pool *pool, int32_t slot0, int32_t count, float *out_params,
+                     double *out_cov, uint32_t *status, double *chi2);
+int lasp_pool_destroy(lasp_pool *pool);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *lasp_last_error(void);

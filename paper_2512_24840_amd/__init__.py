@@ -8,10 +8,14 @@ from .lasp import (  # noqa: F401
     Arms,
     DEFAULT_BOX,
     FitResult,
+    KERNELS,
     LaspError,
+    Pool,
     fit_group,
     forward,
     library_path,
     load,
+    profile_enable,
+    profile_read,
     release,
 )

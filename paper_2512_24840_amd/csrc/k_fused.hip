@@ -79,6 +79,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   float *sSp = reinterpret_cast<float *>(sScal + 20);  // [kMaxArms]
 
   const int spec = blockIdx.x;
+  if (ADJ && !slot_active(s, spec)) return;  // finished slot of a pool: no step
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int P = g.P, M = g.M;
   const int j0 = tid * kNPL;           // first pixel (and basis column) of this lane

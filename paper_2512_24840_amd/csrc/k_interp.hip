@@ -6,6 +6,15 @@
 // v_mfma_f32_16x16x4f32 operand layout (wave64, one block):
 //   A[i][k]: lane i + 16 k      B[k][j]: lane j + 16 k
 //   D[i][j]: lane j + 16 (i / 4), register i % 4
+// v_mfma_f32_16x16x32_bf16: lane l supplies row i = l % 16 of A (column
+// j = l % 16 of B) with eight k values; A and B use the same k assignment,
+// so the sum over k does not depend on which eight each lane carries.
+//
+// BF16x3: x = x_hi + x_lo with x_hi = bf16(x), x_lo = bf16(x - x_hi); a
+// product is a_hi b_hi + a_hi b_lo + a_lo b_hi (the dropped a_lo b_lo is
+// 2^-16 relative), accumulated in FP32.  In the forward contraction the
+// constant monomial's row (phi_0 = 1) is added in FP32 exactly and only
+// rows 1..19 go through BF16x3.
 #include "lasp_internal.h"
 
 namespace lasp {
@@ -26,14 +35,127 @@ __device__ inline void feature_row(const float *u, int t, float *out) {
   }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
+
+// Round to nearest even (finite inputs).
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline void split8(const float *x, bf16x8 &hi, bf16x8 &lo) {
+  ushort8 h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint16_t a = f2bf(x[e]);
+    h[e] = a;
+    l[e] = f2bf(x[e] - bf2f(a));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+
+// hi/lo copies of the padded basis: [20][ldF] for the adjoint contraction and
+// [ldF][32] (k-major, rows 1..19, zeros elsewhere) for the forward one.
+__global__ void k_split_basis(Geometry g, State s) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ldF) return;
+#pragma unroll 1
+  for (int k = 0; k < 32; ++k) {
+    uint16_t hi = 0, lo = 0;
+    if (k < kNB) {
+      const float x = s.basis[(size_t)k * g.ldF + c];
+      hi = f2bf(x);
+      lo = f2bf(x - bf2f(hi));
+      s.basis_hi[(size_t)k * g.ldF + c] = hi;
+      s.basis_lo[(size_t)k * g.ldF + c] = lo;
+    }
+    const bool fwd = k >= 1 && k < kNB;
+    s.basis_thi[(size_t)c * 32 + k] = fwd ? hi : 0;
+    s.basis_tlo[(size_t)c * 32 + k] = fwd ? lo : 0;
+  }
+}
+
+// BF16x3 variant of k_interp_fwd (same grid and output layout).
+__global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, int rows_per_spec, int skip_done) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rows = g.B * rows_per_spec;
+  const int r0 = blockIdx.y * 16;
+  const int my_row = r0 + (lane & 15);
+  const int kq = lane >> 4;
+  if (skip_done && s.target) {
+    bool any = false;
+    for (int r = 0; r < 16; ++r) {
+      const int row = r0 + r;
+      any = any || (row < rows && slot_active(s, row / rows_per_spec));
+    }
+    if (!any) return;
+  }
+  bf16x8 b_hi, b_lo;
+  float phi0 = 0.f;
+  {
+    float phi[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) phi[k] = 0.f;
+    if (my_row < rows) {
+      const int spec = my_row / rows_per_spec;
+      const int t = my_row - spec * rows_per_spec;
+      feature_row(s.u + (size_t)spec * kNP, t, phi);
+    }
+    phi0 = phi[0];
+    phi[0] = 0.f;  // constant row added in FP32 below
+    float sel[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float v = phi[e];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        if (kq == q) v = phi[8 * q + e];
+      sel[e] = v;
+    }
+    split8(sel, b_hi, b_lo);
+  }
+  // phi_0 of the spectrum whose outputs this lane holds (column j = lane % 16)
+  const int cbase = (blockIdx.x * 4 + wave) * (16 * kFwdTiles);
+  for (int n = 0; n < kFwdTiles; ++n) {
+    const int c0 = cbase + 16 * n;
+    if (c0 >= g.ldF) break;
+    const uint16_t *ah = s.basis_thi + (size_t)(c0 + (lane & 15)) * 32 + 8 * kq;
+    const uint16_t *al = s.basis_tlo + (size_t)(c0 + (lane & 15)) * 32 + 8 * kq;
+    const bf16x8 a_hi = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(ah));
+    const bf16x8 a_lo = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(al));
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, b_hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_hi, acc, 0, 0, 0);
+    if (my_row < rows) {
+      const float4 b0 = *reinterpret_cast<const float4 *>(s.basis + c0 + 4 * kq);
+      float4 *dst = reinterpret_cast<float4 *>(s.fp + (size_t)my_row * g.ldF + c0 + 4 * kq);
+      *dst = make_float4(fmaf(phi0, b0.x, acc[0]), fmaf(phi0, b0.y, acc[1]),
+                         fmaf(phi0, b0.z, acc[2]), fmaf(phi0, b0.w, acc[3]));
+    }
+  }
+}
+
 // F'[r][c] = sum_k Phi[r][k] basis[k][c] for r < rows (rows = B or 4B with
 // derivative rows).  Grid: (ldF / (64 * kFwdTiles), ceil(rows / 16)).
-__global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int rows_per_spec) {
+__global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int rows_per_spec, int skip_done) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rows = g.B * rows_per_spec;
   const int r0 = blockIdx.y * 16;
   const int my_row = r0 + (lane & 15);
   const int kq = lane >> 4;  // k offset inside a group of 4
+  if (skip_done && s.target) {
+    bool any = false;
+    for (int r = 0; r < 16; ++r) {
+      const int row = r0 + r;
+      any = any || (row < rows && slot_active(s, row / rows_per_spec));
+    }
+    if (!any) return;
+  }
 
   float bv[5];
   {
@@ -70,6 +192,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
 // J = chi2/n_eff with respect to u and one Adam step (or, with grad_out,
 // the gradient written out and no update).  One workgroup = 16 spectra; its
 // four waves split the columns and combine through LDS.
+template <bool BF16>
 __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg adam,
                                                     int do_adam, float *grad_out) {
   __shared__ float red[4][16][32];
@@ -80,29 +203,71 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
   const int kq = lane >> 4;
   const bool row_ok = s0 + i_row < g.B;
   const float *fb_row = s.fbar + (size_t)(s0 + i_row) * g.ldF;
-  const float *b0_row = s.basis + (size_t)i_row * g.ldF;
   const bool b1_ok = i_row < kNB - 16;
-  const float *b1_row = s.basis + (size_t)(16 + (b1_ok ? i_row : 0)) * g.ldF;
+  const int b1 = 16 + (b1_ok ? i_row : 0);
+  if (s.target) {  // the whole tile finished: nothing to do (uniform over the block)
+    bool any = false;
+    for (int r = 0; r < 16; ++r) any = any || (s0 + r < g.B && slot_active(s, s0 + r));
+    if (!any) return;
+  }
 
   floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  const int per_wave = ((g.ldF / 16 + 3) / 4) * 16;
+  const int per_wave = g.ldF / 4;  // ldF is a multiple of 64
   const int cb = wave * per_wave;
-  const int ce = min(cb + per_wave, g.ldF);
-  for (int c = cb; c < ce; c += 16) {
-    const int cc = c + 4 * kq;
-    float4 fa = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (row_ok) fa = *reinterpret_cast<const float4 *>(fb_row + cc);
-    const float4 b0 = *reinterpret_cast<const float4 *>(b0_row + cc);
-    float4 b1 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (b1_ok) b1 = *reinterpret_cast<const float4 *>(b1_row + cc);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.x, b0.x, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.x, b1.x, acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.y, b0.y, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.y, b1.y, acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.z, b0.z, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.z, b1.z, acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.w, b0.w, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.w, b1.w, acc1, 0, 0, 0);
+  const int ce = cb + per_wave;
+  if (!BF16) {
+    const float *b0_row = s.basis + (size_t)i_row * g.ldF;
+    const float *b1_row = s.basis + (size_t)b1 * g.ldF;
+    for (int c = cb; c < ce; c += 16) {
+      const int cc = c + 4 * kq;
+      float4 fa = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row_ok) fa = *reinterpret_cast<const float4 *>(fb_row + cc);
+      const float4 bv0 = *reinterpret_cast<const float4 *>(b0_row + cc);
+      float4 bv1 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (b1_ok) bv1 = *reinterpret_cast<const float4 *>(b1_row + cc);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.x, bv0.x, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.x, bv1.x, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.y, bv0.y, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.y, bv1.y, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.z, bv0.z, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.z, bv1.z, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.w, bv0.w, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.w, bv1.w, acc1, 0, 0, 0);
+    }
+  } else {
+    const uint16_t *h0 = s.basis_hi + (size_t)i_row * g.ldF;
+    const uint16_t *l0 = s.basis_lo + (size_t)i_row * g.ldF;
+    const uint16_t *h1 = s.basis_hi + (size_t)b1 * g.ldF;
+    const uint16_t *l1 = s.basis_lo + (size_t)b1 * g.ldF;
+    const bf16x8 zero = __builtin_bit_cast(bf16x8, ushort8{0, 0, 0, 0, 0, 0, 0, 0});
+    for (int c = cb; c < ce; c += 32) {
+      const int cc = c + 8 * kq;
+      float fa[8];
+      if (row_ok) {
+        const float4 x0 = *reinterpret_cast<const float4 *>(fb_row + cc);
+        const float4 x1 = *reinterpret_cast<const float4 *>(fb_row + cc + 4);
+        fa[0] = x0.x; fa[1] = x0.y; fa[2] = x0.z; fa[3] = x0.w;
+        fa[4] = x1.x; fa[5] = x1.y; fa[6] = x1.z; fa[7] = x1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) fa[e] = 0.f;
+      }
+      bf16x8 a_hi, a_lo;
+      split8(fa, a_hi, a_lo);
+      const bf16x8 bh0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h0 + cc));
+      const bf16x8 bl0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l0 + cc));
+      bf16x8 bh1 = zero, bl1 = zero;
+      if (b1_ok) {
+        bh1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h1 + cc));
+        bl1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l1 + cc));
+      }
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh1, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl1, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh1, acc1, 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -136,7 +301,7 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
 #pragma unroll
       for (int a = 0; a < kNP; ++a) grad_out[(size_t)spec * kNP + a] = grad[a];
     }
-    if (do_adam) {
+    if (do_adam && slot_active(s, spec)) {
       const int step = s.t[spec] + 1;
       s.t[spec] = step;
       const float bc1 = 1.f - powf(adam.beta1, (float)step);
@@ -163,20 +328,33 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
 
 hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, int bf16x3,
                              hipStream_t st) {
-  (void)bf16x3;
   const int rows_per_spec = deriv_rows ? 4 : 1;
   const int rows = g.B * rows_per_spec;
   const int cols_per_block = 4 * 16 * kFwdTiles;
   dim3 grid((g.ldF + cols_per_block - 1) / cols_per_block, (rows + 15) / 16);
-  hipLaunchKernelGGL(k_interp_fwd, grid, dim3(256), 0, st, g, s, rows_per_spec);
+  // derivative rows are only formed for final evaluations: never skip those
+  const int skip_done = deriv_rows ? 0 : 1;
+  if (bf16x3)
+    hipLaunchKernelGGL(k_interp_fwd_bf16, grid, dim3(256), 0, st, g, s, rows_per_spec, skip_done);
+  else
+    hipLaunchKernelGGL(k_interp_fwd, grid, dim3(256), 0, st, g, s, rows_per_spec, skip_done);
   return hipGetLastError();
 }
 
 hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *adam,
-                             float *grad_out, hipStream_t st) {
+                             float *grad_out, int bf16x3, hipStream_t st) {
   AdamCfg a = adam ? *adam : AdamCfg{0.f, 0.f, 0.f, 0.f};
-  hipLaunchKernelGGL(k_interp_bwd, dim3((g.B + 15) / 16), dim3(256), 0, st, g, s, a,
-                     adam ? 1 : 0, grad_out);
+  if (bf16x3)
+    hipLaunchKernelGGL(k_interp_bwd<true>, dim3((g.B + 15) / 16), dim3(256), 0, st, g, s, a,
+                       adam ? 1 : 0, grad_out);
+  else
+    hipLaunchKernelGGL(k_interp_bwd<false>, dim3((g.B + 15) / 16), dim3(256), 0, st, g, s, a,
+                       adam ? 1 : 0, grad_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_basis(const Geometry &g, const State &s, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_basis, dim3((g.ldF + 255) / 256), dim3(256), 0, st, g, s);
   return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
                                                         double blo3, double blo4, double bhi0,
                                                         double bhi1, double bhi2, double bhi3,
                                                         double bhi4, float quantile,
-                                                        int init_state) {
+                                                        int init_state, int target_steps) {
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sh[2];
   __shared__ int red_n[kPrepBlock / 64];
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
         s.v[(size_t)spec * kNP + t] = 0.f;
       }
       s.t[spec] = 0;
+      if (s.target) s.target[spec] = target_steps;
     }
   }
 }
@@ -175,14 +176,37 @@ __global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double
   if (chi2_out) chi2_out[spec] = s.chi2[spec];
 }
 
+// Per-spectrum results of a forward evaluation: chi2, the objective
+// J = chi2 / n_eff of Eq. 9 (read per spectrum), n_eff and status.
+__global__ void k_outputs(Geometry g, State s, double *chi2_out, float *J_out, int32_t *neff_out,
+                          uint32_t *status_out) {
+  const int spec = blockIdx.x * blockDim.x + threadIdx.x;
+  if (spec >= g.B) return;
+  const double c = s.chi2[spec];
+  const int n = s.neff[spec];
+  if (chi2_out) chi2_out[spec] = c;
+  if (J_out) J_out[spec] = n > 0 ? (float)(c / (double)n) : 0.f;
+  if (neff_out) neff_out[spec] = n;
+  if (status_out) status_out[spec] = s.status[spec];
+}
+
 }  // namespace
+
+hipError_t launch_outputs(const Geometry &g, const State &s, double *chi2_out, float *J_out,
+                          int32_t *neff_out, uint32_t *status_out, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_outputs, dim3((g.B + bs - 1) / bs), dim3(bs), 0, st, g, s, chi2_out, J_out,
+                     neff_out, status_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_prepare(const Geometry &g, const State &s, const float *obs, const float *ivar,
                           const float *init_params, const double *lo, const double *hi,
-                          float weight_quantile, int init_state, hipStream_t st) {
+                          float weight_quantile, int init_state, int target_steps,
+                          hipStream_t st) {
   hipLaunchKernelGGL(k_prepare, dim3(g.B), dim3(kPrepBlock), 0, st, g, s, obs, ivar, init_params,
                      lo[0], lo[1], lo[2], lo[3], lo[4], hi[0], hi[1], hi[2], hi[3], hi[4],
-                     weight_quantile, init_state);
+                     weight_quantile, init_state, target_steps);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <map>
+#include <vector>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -56,12 +57,66 @@ hipError_t grow(T *&p, size_t &cap, size_t need) {
 
 void free_ws(Workspace *w) {
   State &s = w->s;
-  void *ptrs[] = {s.u, s.m, s.v, s.t, s.ow, s.wscale, s.neff, s.status, s.fp, s.fbar, s.g45, s.chi2,
-                  s.basis, s.basis_hi, s.basis_lo};
+  void *ptrs[] = {s.u,    s.m,     s.v,        s.t,        s.ow,       s.wscale,   s.neff,
+                  s.status, s.fp,  s.fbar,     s.g45,      s.chi2,     s.basis,    s.basis_hi,
+                  s.basis_lo, s.basis_thi, s.basis_tlo};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   w->s = State{};
   w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = 0;
+}
+
+// Grows the buffers of w to hold g.B spectra of geometry g (fp_rows rows of F'
+// per spectrum).  Earlier work on the stream may still use old buffers, so
+// the stream is synchronised before anything is freed.
+int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, hipStream_t st) {
+  const size_t B = (size_t)g.B;
+  const size_t need_ow = B * lasp::kNPL * g.block;
+  const size_t need_fp = B * fp_rows * g.ldF;
+  const size_t need_fbar = B * g.ldF;
+  const size_t need_basis = (size_t)lasp::kNB * g.ldF;
+  const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
+                      need_fbar > w->cap_fbar || need_basis > w->cap_basis || !w->s.u;
+  if (!regrow) return LASP_OK;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+  State &s = w->s;
+  const size_t cb = w->cap_B;
+  size_t c1 = cb, c2 = cb, c3 = cb, c4 = cb, c5 = cb, c6 = cb, c7 = cb, c8 = cb, c9 = cb;
+  hipError_t r = hipSuccess;
+  if (B > cb || !s.u) {
+    r = grow(s.u, c1, B * lasp::kNP);
+    if (r == hipSuccess) r = grow(s.m, c2, B * lasp::kNP);
+    if (r == hipSuccess) r = grow(s.v, c3, B * lasp::kNP);
+    if (r == hipSuccess) r = grow(s.t, c4, B);
+    if (r == hipSuccess) r = grow(s.wscale, c5, B);
+    if (r == hipSuccess) r = grow(s.neff, c6, B);
+    if (r == hipSuccess) r = grow(s.status, c7, B);
+    if (r == hipSuccess) r = grow(s.g45, c8, B * 2);
+    if (r == hipSuccess) r = grow(s.chi2, c9, B);
+    if (r == hipSuccess) w->cap_B = B;
+  }
+  if (r == hipSuccess) r = grow(s.ow, w->cap_ow, need_ow);
+  if (r == hipSuccess) r = grow(s.fp, w->cap_fp, need_fp);
+  if (r == hipSuccess) r = grow(s.fbar, w->cap_fbar, need_fbar);
+  if (r == hipSuccess) {
+    size_t cap = w->cap_basis;
+    r = grow(s.basis, cap, need_basis);
+    size_t cap2 = w->cap_basis, cap3 = w->cap_basis;
+    size_t cap4 = w->cap_basis * 32 / lasp::kNB, cap5 = cap4;
+    if (r == hipSuccess) r = grow(s.basis_hi, cap2, need_basis);
+    if (r == hipSuccess) r = grow(s.basis_lo, cap3, need_basis);
+    if (r == hipSuccess) r = grow(s.basis_thi, cap4, (size_t)32 * g.ldF);
+    if (r == hipSuccess) r = grow(s.basis_tlo, cap5, (size_t)32 * g.ldF);
+    if (r == hipSuccess) w->cap_basis = need_basis;
+  }
+  if (r != hipSuccess) {
+    free_ws(w);
+    (void)hipGetLastError();
+    return fail(r == hipErrorOutOfMemory ? LASP_E_NOMEM : LASP_E_DEVICE,
+                std::string("device allocation: ") + hipGetErrorString(r));
+  }
+  return LASP_OK;
 }
 
 int get_workspace(const Geometry &g, int fp_rows, hipStream_t st, Workspace **out) {
@@ -77,53 +132,30 @@ int get_workspace(const Geometry &g, int fp_rows, hipStream_t st, Workspace **ou
     w->stream = st;
     g_ws[key] = w;
   }
-  const size_t B = (size_t)g.B;
-  const size_t need_ow = B * lasp::kNPL * g.block;
-  const size_t need_fp = B * fp_rows * g.ldF;
-  const size_t need_fbar = B * g.ldF;
-  const size_t need_basis = (size_t)lasp::kNB * g.ldF;
-  const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
-                      need_fbar > w->cap_fbar || need_basis > w->cap_basis || !w->s.u;
-  if (regrow) {
-    // earlier work on this stream may still use the old buffers
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
-    State &s = w->s;
-    size_t cb = w->cap_B;
-    size_t c1 = cb, c2 = cb, c3 = cb, c4 = cb, c5 = cb, c6 = cb, c7 = cb, c8 = cb, c9 = cb;
-    hipError_t r = hipSuccess;
-    if (B > cb || !s.u) {
-      r = grow(s.u, c1, B * lasp::kNP);
-      if (r == hipSuccess) r = grow(s.m, c2, B * lasp::kNP);
-      if (r == hipSuccess) r = grow(s.v, c3, B * lasp::kNP);
-      if (r == hipSuccess) r = grow(s.t, c4, B);
-      if (r == hipSuccess) r = grow(s.wscale, c5, B);
-      if (r == hipSuccess) r = grow(s.neff, c6, B);
-      if (r == hipSuccess) r = grow(s.status, c7, B);
-      if (r == hipSuccess) r = grow(s.g45, c8, B * 2);
-      if (r == hipSuccess) r = grow(s.chi2, c9, B);
-      if (r == hipSuccess) w->cap_B = B;
-    }
-    if (r == hipSuccess) r = grow(s.ow, w->cap_ow, need_ow);
-    if (r == hipSuccess) r = grow(s.fp, w->cap_fp, need_fp);
-    if (r == hipSuccess) r = grow(s.fbar, w->cap_fbar, need_fbar);
-    if (r == hipSuccess) {
-      size_t cap = w->cap_basis;
-      r = grow(s.basis, cap, need_basis);
-      size_t cap2 = w->cap_basis, cap3 = w->cap_basis;
-      if (r == hipSuccess) r = grow(s.basis_hi, cap2, need_basis);
-      if (r == hipSuccess) r = grow(s.basis_lo, cap3, need_basis);
-      if (r == hipSuccess) w->cap_basis = need_basis;
-    }
-    if (r != hipSuccess) {
-      free_ws(w);
-      (void)hipGetLastError();
-      return fail(r == hipErrorOutOfMemory ? LASP_E_NOMEM : LASP_E_DEVICE,
-                  std::string("device allocation: ") + hipGetErrorString(r));
-    }
-  }
+  int rc = ensure_buffers(w, g, fp_rows, st);
+  if (rc) return rc;
   *out = w;
   return LASP_OK;
+}
+
+// Per-spectrum pointers shifted to start at slot0 (fp_rows rows of F' each).
+State offset_state(const State &s, const Geometry &g, int slot0, int fp_rows) {
+  State o = s;
+  const size_t k = (size_t)slot0;
+  o.u += k * lasp::kNP;
+  o.m += k * lasp::kNP;
+  o.v += k * lasp::kNP;
+  o.t += k;
+  if (o.target) o.target += k;
+  o.ow += k * lasp::kNPL * g.block;
+  o.wscale += k;
+  o.neff += k;
+  o.status += k;
+  o.g45 += 2 * k;
+  o.chi2 += k;
+  o.fp += k * fp_rows * g.ldF;
+  o.fbar += k * g.ldF;
+  return o;
 }
 
 // Validates options and the wavelength grid and fills the geometry.
@@ -135,8 +167,8 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
   if (o->margin < 1 || o->margin > 80) return fail(LASP_E_ARG, "margin must be in [1, 80]");
   if (!(o->degree == 4 || o->degree == 6 || o->degree == 8 || o->degree == 10))
     return fail(LASP_E_UNSUPPORTED, "degree must be one of 4, 6, 8, 10");
-  if (o->precision != LASP_PREC_FP32)
-    return fail(LASP_E_UNSUPPORTED, "only LASP_PREC_FP32 is available in this build");
+  if (o->precision != LASP_PREC_FP32 && o->precision != LASP_PREC_BF16X3)
+    return fail(LASP_E_UNSUPPORTED, "precision must be LASP_PREC_FP32 or LASP_PREC_BF16X3");
   for (int t = 0; t < LASP_N_PAR; ++t)
     if (!(o->box_hi[t] > o->box_lo[t]) || !isfinite(o->box_lo[t]) || !isfinite(o->box_hi[t]))
       return fail(LASP_E_ARG, "box_hi must exceed box_lo (finite)");
@@ -167,7 +199,7 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
   g->P = P;
   g->M = o->margin;
   g->Pe = P + 2 * o->margin;
-  g->ldF = (g->Pe + 63) & ~63;
+  g->ldF = (g->Pe + 127) & ~127;
   g->nd = o->degree + 1;
   g->block = 0;
   for (int b : {128, 256, 512})
@@ -213,12 +245,71 @@ __global__ void k_copy_basis(const float *src, float *dst, int Pe, int ldF) {
     dst[(size_t)k * ldF + c] = c < Pe ? src[(size_t)k * Pe + c] : 0.f;
 }
 
-int copy_basis(const Geometry &g, const State &s, const float *basis, hipStream_t st) {
+int copy_basis(const Geometry &g, const State &s, const float *basis, int bf16x3,
+               hipStream_t st) {
   hipLaunchKernelGGL(k_copy_basis, dim3((g.ldF + 255) / 256, lasp::kNB), dim3(256), 0, st, basis,
                      s.basis, g.Pe, g.ldF);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && bf16x3) e = lasp::launch_split_basis(g, s, st);
   return e == hipSuccess ? LASP_OK : dev_fail(e, "copy basis");
 }
+
+// ---- optional kernel timing (lasp_profile_*) ------------------------------
+struct ProfRecord {
+  int cls;
+  hipEvent_t beg, end;
+};
+uint32_t g_prof_mask = 0;
+std::vector<ProfRecord> g_prof;       // recorded, not yet read
+std::vector<hipEvent_t> g_event_pool;  // free events
+double g_prof_ms[LASP_NK];
+int64_t g_prof_n[LASP_NK];
+
+hipEvent_t pool_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when its class is being timed.
+struct ProfScope {
+  int cls;
+  hipStream_t st;
+  hipEvent_t beg = nullptr;
+  ProfScope(int c, hipStream_t s) : cls(c), st(s) {
+    if (g_prof_mask & (1u << c)) {
+      beg = pool_event();
+      if (beg) (void)hipEventRecord(beg, st);
+    }
+  }
+  ~ProfScope() {
+    if (!beg) return;
+    hipEvent_t end = pool_event();
+    if (!end) return;
+    (void)hipEventRecord(end, st);
+    g_prof.push_back(ProfRecord{cls, beg, end});
+  }
+};
+
+void prof_drain() {
+  for (auto &r : g_prof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.end) == hipSuccess && hipEventElapsedTime(&ms, r.beg, r.end) == hipSuccess) {
+      g_prof_ms[r.cls] += ms;
+      g_prof_n[r.cls] += 1;
+    }
+    g_event_pool.push_back(r.beg);
+    g_event_pool.push_back(r.end);
+  }
+  g_prof.clear();
+}
+
+#define LASP_TIMED(cls, st) ProfScope prof_scope_##__LINE__((cls), (st))
 
 #define LASP_CHECK(call, what)                 \
   do {                                         \
@@ -252,6 +343,27 @@ void lasp_default_opts(lasp_opts *o) {
 
 const char *lasp_last_error(void) { return g_err.c_str(); }
 
+int lasp_profile_enable(uint32_t mask) {
+  prof_drain();
+  for (int k = 0; k < LASP_NK; ++k) {
+    g_prof_ms[k] = 0.0;
+    g_prof_n[k] = 0;
+  }
+  g_prof_mask = mask;
+  return LASP_OK;
+}
+
+int lasp_profile_read(double *total_ms, int64_t *launches, int32_t n) {
+  if (n < 0 || n > LASP_NK || (n > 0 && (!total_ms || !launches)))
+    return fail(LASP_E_ARG, "lasp_profile_read: bad arguments");
+  prof_drain();
+  for (int k = 0; k < n; ++k) {
+    total_ms[k] = g_prof_ms[k];
+    launches[k] = g_prof_n[k];
+  }
+  return LASP_OK;
+}
+
 void lasp_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int cur = 0;
@@ -283,34 +395,53 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   rc = get_workspace(g, out_cov ? 4 : 1, st, &w);
   if (rc) return rc;
   State s = w->s;
-  rc = copy_basis(g, s, basis, st);
+  const int bf16 = opts->precision == LASP_PREC_BF16X3;
+  rc = copy_basis(g, s, basis, bf16, st);
   if (rc) return rc;
-  LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, init_params, opts->box_lo, opts->box_hi,
-                                  opts->weight_quantile, 1, st),
-             "prepare");
+  {
+    LASP_TIMED(LASP_K_PREPARE, st);
+    LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, init_params, opts->box_lo, opts->box_hi,
+                                    opts->weight_quantile, 1, n_steps, st),
+               "prepare");
+  }
   const lasp::AdamCfg adam{opts->lr, opts->beta1, opts->beta2, opts->eps};
   s.fp_stride = g.ldF;
   for (int it = 0; it < n_steps; ++it) {
-    LASP_CHECK(lasp::launch_interp_fwd(g, s, 0, 0, st), "interpolator contraction");
-    LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, st), "fused pass");
-    LASP_CHECK(lasp::launch_interp_bwd(g, s, &adam, nullptr, st), "adjoint contraction + Adam");
+    {
+      LASP_TIMED(LASP_K_INTERP_FWD, st);
+      LASP_CHECK(lasp::launch_interp_fwd(g, s, 0, bf16, st), "interpolator contraction");
+    }
+    {
+      LASP_TIMED(LASP_K_FUSED, st);
+      LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, st), "fused pass");
+    }
+    {
+      LASP_TIMED(LASP_K_INTERP_BWD, st);
+      LASP_CHECK(lasp::launch_interp_bwd(g, s, &adam, nullptr, bf16, st), "adjoint contraction + Adam");
+    }
   }
   // chi2 and status at the returned parameters; derivative rows for the covariance
   s.fp_stride = out_cov ? 4 * g.ldF : g.ldF;
-  LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, 0, st), "interpolator contraction");
+  LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, bf16, st), "interpolator contraction");
   LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, st), "fused pass");
-  if (out_cov)
+  if (out_cov) {
+    LASP_TIMED(LASP_K_COV, st);
     LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, nullptr, st),
                "covariance");
-  LASP_CHECK(lasp::launch_finalize(g, s, opts->box_lo, opts->box_hi, out_params, opts->status,
-                                   opts->out_chi2, st),
-             "finalize");
+  }
+  {
+    LASP_TIMED(LASP_K_FINALIZE, st);
+    LASP_CHECK(lasp::launch_finalize(g, s, opts->box_lo, opts->box_hi, out_params, opts->status,
+                                     opts->out_chi2, st),
+               "finalize");
+  }
   return LASP_OK;
 }
 
 int lasp_forward(const float *obs, const float *ivar, const double *wave_grid, const float *basis,
-                 const float *u, float *out_model, double *out_chi2, int32_t *out_neff,
-                 float *out_grad, float *out_jac, const lasp_opts *opts) {
+                 const float *u, float *out_model, double *out_chi2, float *out_J,
+                 int32_t *out_neff, float *out_grad, float *out_jac, double *out_cov,
+                 const lasp_opts *opts) {
   g_err.clear();
   Geometry g;
   int rc = make_geometry(opts, wave_grid, &g);
@@ -319,34 +450,192 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid, c
     return fail(LASP_E_ARG, "obs, ivar, basis, u and out_chi2 are required");
   if (g.B == 0) return LASP_OK;
   hipStream_t st = (hipStream_t)opts->stream;
+  const bool rows4 = out_jac || out_cov;
   Workspace *w = nullptr;
-  rc = get_workspace(g, out_jac ? 4 : 1, st, &w);
+  rc = get_workspace(g, rows4 ? 4 : 1, st, &w);
   if (rc) return rc;
   State s = w->s;
-  rc = copy_basis(g, s, basis, st);
+  const int bf16 = opts->precision == LASP_PREC_BF16X3;
+  rc = copy_basis(g, s, basis, bf16, st);
   if (rc) return rc;
-  LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, nullptr, opts->box_lo, opts->box_hi,
-                                  opts->weight_quantile, 0, st),
-             "prepare");
+  {
+    LASP_TIMED(LASP_K_PREPARE, st);
+    LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, nullptr, opts->box_lo, opts->box_hi,
+                                    opts->weight_quantile, 0, 0, st),
+               "prepare");
+  }
   LASP_CHECK(hipMemcpyAsync(s.u, u, sizeof(float) * lasp::kNP * g.B, hipMemcpyDeviceToDevice, st),
              "copy u");
-  s.fp_stride = out_jac ? 4 * g.ldF : g.ldF;
-  LASP_CHECK(lasp::launch_interp_fwd(g, s, out_jac ? 1 : 0, 0, st), "interpolator contraction");
-  LASP_CHECK(lasp::launch_fused(g, s, out_grad ? 1 : 0, out_model, st), "fused pass");
-  if (out_grad)
-    LASP_CHECK(lasp::launch_interp_bwd(g, s, nullptr, out_grad, st), "adjoint contraction");
-  if (out_jac)
-    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, nullptr, out_jac, st),
-               "model Jacobian");
-  LASP_CHECK(hipMemcpyAsync(out_chi2, s.chi2, sizeof(double) * g.B, hipMemcpyDeviceToDevice, st),
-             "copy chi2");
-  if (out_neff)
-    LASP_CHECK(hipMemcpyAsync(out_neff, s.neff, sizeof(int) * g.B, hipMemcpyDeviceToDevice, st),
-               "copy n_eff");
-  if (opts->status)
-    LASP_CHECK(hipMemcpyAsync(opts->status, s.status, sizeof(uint32_t) * g.B,
-                              hipMemcpyDeviceToDevice, st),
-               "copy status");
+  s.fp_stride = rows4 ? 4 * g.ldF : g.ldF;
+  {
+    LASP_TIMED(LASP_K_INTERP_FWD, st);
+    LASP_CHECK(lasp::launch_interp_fwd(g, s, rows4 ? 1 : 0, bf16, st), "interpolator contraction");
+  }
+  {
+    LASP_TIMED(LASP_K_FUSED, st);
+    LASP_CHECK(lasp::launch_fused(g, s, out_grad ? 1 : 0, out_model, st), "fused pass");
+  }
+  if (out_grad) {
+    LASP_TIMED(LASP_K_INTERP_BWD, st);
+    LASP_CHECK(lasp::launch_interp_bwd(g, s, nullptr, out_grad, bf16, st), "adjoint contraction");
+  }
+  if (rows4) {
+    LASP_TIMED(LASP_K_COV, st);
+    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, out_jac, st),
+               "covariance / model Jacobian");
+  }
+  LASP_CHECK(lasp::launch_outputs(g, s, out_chi2, out_J, out_neff, opts->status, st), "outputs");
+  return LASP_OK;
+}
+
+
+// ---------------------------------------------------------------- pools --
+}  // extern "C"
+
+struct lasp_pool {
+  Geometry g;          // g.B = capacity
+  lasp_opts opts;
+  hipStream_t st;
+  int device;
+  int bf16;
+  Workspace w;
+  int *target;
+};
+
+namespace {
+int pool_geometry(const lasp_pool *p, int count, Geometry *g) {
+  *g = p->g;
+  g->B = count;
+  return LASP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t lasp_pool_slot_bytes(const lasp_opts *opts, const double *wave_grid) {
+  Geometry g;
+  if (make_geometry(opts, wave_grid, &g)) return 0;
+  return (size_t)lasp::kNPL * g.block * 8 + (size_t)5 * g.ldF * 4 + 64 + 3 * 20 + 40;
+}
+
+int lasp_pool_create(const double *wave_grid, const float *basis, const lasp_opts *opts,
+                     lasp_pool **out) {
+  g_err.clear();
+  if (!out) return fail(LASP_E_ARG, "out is NULL");
+  *out = nullptr;
+  Geometry g;
+  int rc = make_geometry(opts, wave_grid, &g);
+  if (rc) return rc;
+  if (!basis) return fail(LASP_E_ARG, "basis is NULL");
+  if (g.B < 1) return fail(LASP_E_ARG, "pool capacity (n_spec) must be >= 1");
+  lasp_pool *p = new lasp_pool();
+  p->g = g;
+  p->opts = *opts;
+  p->st = (hipStream_t)opts->stream;
+  p->bf16 = opts->precision == LASP_PREC_BF16X3;
+  p->target = nullptr;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return dev_fail(e, "hipGetDevice");
+  }
+  rc = ensure_buffers(&p->w, g, 4, p->st);
+  if (!rc) {
+    e = hipMalloc((void **)&p->target, sizeof(int) * g.B);
+    if (e != hipSuccess) rc = fail(LASP_E_NOMEM, "pool target array");
+  }
+  if (!rc) {
+    p->w.s.target = p->target;
+    e = hipMemsetAsync(p->target, 0, sizeof(int) * g.B, p->st);
+    if (e == hipSuccess) e = hipMemsetAsync(p->w.s.t, 0, sizeof(int) * g.B, p->st);
+    if (e != hipSuccess) rc = dev_fail(e, "pool init");
+  }
+  if (!rc) rc = copy_basis(g, p->w.s, basis, p->bf16, p->st);
+  if (rc) {
+    lasp_pool_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return LASP_OK;
+}
+
+int lasp_pool_load(lasp_pool *p, int32_t slot0, int32_t count, const float *obs,
+                   const float *ivar, const float *init_params, int32_t n_steps) {
+  g_err.clear();
+  if (!p || !obs || !ivar || !init_params) return fail(LASP_E_ARG, "NULL argument");
+  if (slot0 < 0 || count < 1 || slot0 + count > p->g.B || n_steps < 0)
+    return fail(LASP_E_ARG, "slot range outside the pool or n_steps < 0");
+  Geometry g;
+  pool_geometry(p, count, &g);
+  State s = offset_state(p->w.s, p->g, slot0, 4);
+  LASP_TIMED(LASP_K_PREPARE, p->st);
+  LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, init_params, p->opts.box_lo, p->opts.box_hi,
+                                  p->opts.weight_quantile, 1, n_steps, p->st),
+             "prepare");
+  return LASP_OK;
+}
+
+int lasp_pool_step(lasp_pool *p, int32_t slot_end, int32_t k) {
+  g_err.clear();
+  if (!p) return fail(LASP_E_ARG, "pool is NULL");
+  if (slot_end < 0 || slot_end > p->g.B || k < 0) return fail(LASP_E_ARG, "bad slot_end or k");
+  if (slot_end == 0 || k == 0) return LASP_OK;
+  Geometry g;
+  pool_geometry(p, slot_end, &g);
+  State s = p->w.s;
+  s.fp_stride = g.ldF;
+  const lasp::AdamCfg adam{p->opts.lr, p->opts.beta1, p->opts.beta2, p->opts.eps};
+  for (int it = 0; it < k; ++it) {
+    {
+      LASP_TIMED(LASP_K_INTERP_FWD, p->st);
+      LASP_CHECK(lasp::launch_interp_fwd(g, s, 0, p->bf16, p->st), "interpolator contraction");
+    }
+    {
+      LASP_TIMED(LASP_K_FUSED, p->st);
+      LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, p->st), "fused pass");
+    }
+    {
+      LASP_TIMED(LASP_K_INTERP_BWD, p->st);
+      LASP_CHECK(lasp::launch_interp_bwd(g, s, &adam, nullptr, p->bf16, p->st),
+                 "adjoint contraction + Adam");
+    }
+  }
+  return LASP_OK;
+}
+
+int lasp_pool_finish(lasp_pool *p, int32_t slot0, int32_t count, float *out_params,
+                     double *out_cov, uint32_t *status, double *chi2) {
+  g_err.clear();
+  if (!p || !out_params) return fail(LASP_E_ARG, "NULL argument");
+  if (slot0 < 0 || count < 1 || slot0 + count > p->g.B)
+    return fail(LASP_E_ARG, "slot range outside the pool");
+  Geometry g;
+  pool_geometry(p, count, &g);
+  const int rows = out_cov ? 4 : 1;
+  State s = offset_state(p->w.s, p->g, slot0, rows);
+  s.target = nullptr;  // the final evaluation covers every slot of the range
+  s.fp_stride = rows * g.ldF;
+  LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, p->bf16, p->st),
+             "interpolator contraction");
+  LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, p->st), "fused pass");
+  if (out_cov) {
+    LASP_TIMED(LASP_K_COV, p->st);
+    LASP_CHECK(lasp::launch_cov(g, s, p->opts.box_lo, p->opts.box_hi, out_cov, nullptr, p->st),
+               "covariance");
+  }
+  LASP_TIMED(LASP_K_FINALIZE, p->st);
+  LASP_CHECK(lasp::launch_finalize(g, s, p->opts.box_lo, p->opts.box_hi, out_params, status,
+                                   chi2, p->st),
+             "finalize");
+  return LASP_OK;
+}
+
+int lasp_pool_destroy(lasp_pool *p) {
+  if (!p) return LASP_OK;
+  (void)hipStreamSynchronize(p->st);
+  free_ws(&p->w);
+  if (p->target) (void)hipFree(p->target);
+  delete p;
   return LASP_OK;
 }
 

@@ -50,6 +50,7 @@ struct State {
   float *m;         // [B][5] Adam first moment
   float *v;         // [B][5] Adam second moment
   int *t;           // [B] Adam step count
+  int *target;      // [B] step count at which a slot stops (NULL: every slot runs)
   float2 *ow;       // [B][kNPL][block] (o/w, W w^2) in lane-major order
   float *wscale;    // [B] flux weight w
   int *neff;        // [B]
@@ -60,8 +61,10 @@ struct State {
   float *g45;       // [B][2] dJ/du4, dJ/du5
   double *chi2;     // [B]
   float *basis;     // [20][ldF] zero-padded copy of the basis
-  uint16_t *basis_hi;  // [20][ldF] bf16 high part (BF16x3)
-  uint16_t *basis_lo;  // [20][ldF] bf16 low part (BF16x3)
+  uint16_t *basis_hi;  // [20][ldF] bf16 high part (BF16x3, adjoint contraction)
+  uint16_t *basis_lo;  // [20][ldF] bf16 low part
+  uint16_t *basis_thi; // [ldF][32] bf16 high part, k-major per column, rows 1..19 (forward)
+  uint16_t *basis_tlo; // [ldF][32] bf16 low part
 };
 
 struct AdamCfg {
@@ -71,18 +74,28 @@ struct AdamCfg {
 // ---------------------------------------------------------------- host side
 hipError_t launch_prepare(const Geometry &g, const State &s, const float *obs, const float *ivar,
                           const float *init_params, const double *box_lo, const double *box_hi,
-                          float weight_quantile, int init_state, hipStream_t st);
+                          float weight_quantile, int init_state, int target_steps, hipStream_t st);
+
+// A spectrum takes Adam steps while t < target (always when target is NULL).
+#ifdef __HIPCC__
+__device__ inline bool slot_active(const State &s, int spec) {
+  return s.target == nullptr || s.t[spec] < s.target[spec];
+}
+#endif
 hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, int bf16x3,
                              hipStream_t st);
 hipError_t launch_fused(const Geometry &g, const State &s, int adjoint, float *model_out,
                         hipStream_t st);
 hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *adam,
-                             float *grad_out, hipStream_t st);
+                             float *grad_out, int bf16x3, hipStream_t st);
+hipError_t launch_split_basis(const Geometry &g, const State &s, hipStream_t st);
 hipError_t launch_finalize(const Geometry &g, const State &s, const double *box_lo,
                            const double *box_hi, float *out_params, uint32_t *status_out,
                            double *chi2_out, hipStream_t st);
 hipError_t launch_cov(const Geometry &g, const State &s, const double *box_lo, const double *box_hi,
                       double *out_cov, float *out_jac, hipStream_t st);
+hipError_t launch_outputs(const Geometry &g, const State &s, double *chi2_out, float *J_out,
+                          int32_t *neff_out, uint32_t *status_out, hipStream_t st);
 bool fused_supported(int block, int nd);
 size_t fused_smem_bytes(const Geometry &g);
 

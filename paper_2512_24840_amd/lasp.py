@@ -31,7 +31,10 @@ PREC = {"fp32": 0, "bf16x3": 1}
 N_BASIS = 20
 N_PAR = 5
 EXPORTED = ("lasp_default_opts", "lasp_fit_group", "lasp_forward", "lasp_last_error",
-            "lasp_release")
+            "lasp_release", "lasp_profile_enable", "lasp_profile_read", "lasp_pool_slot_bytes",
+            "lasp_pool_create", "lasp_pool_load", "lasp_pool_step", "lasp_pool_finish",
+            "lasp_pool_destroy")
+KERNELS = ("prepare", "interp_fwd", "fused", "interp_bwd", "cov", "finalize")
 
 
 class LaspError(RuntimeError):
@@ -84,13 +87,32 @@ def load() -> ctypes.CDLL:
         lib.lasp_fit_group.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32,
                                        ctypes.POINTER(LaspOpts)]
         lib.lasp_fit_group.restype = ctypes.c_int
-        lib.lasp_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+        lib.lasp_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                      ctypes.POINTER(LaspOpts)]
         lib.lasp_forward.restype = ctypes.c_int
         lib.lasp_last_error.argtypes = []
         lib.lasp_last_error.restype = ctypes.c_char_p
         lib.lasp_release.argtypes = []
         lib.lasp_release.restype = None
+        lib.lasp_profile_enable.argtypes = [ctypes.c_uint32]
+        lib.lasp_profile_enable.restype = ctypes.c_int
+        lib.lasp_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        lib.lasp_profile_read.restype = ctypes.c_int
+        lib.lasp_pool_slot_bytes.argtypes = [ctypes.POINTER(LaspOpts), vp]
+        lib.lasp_pool_slot_bytes.restype = ctypes.c_size_t
+        lib.lasp_pool_create.argtypes = [vp, vp, ctypes.POINTER(LaspOpts),
+                                         ctypes.POINTER(ctypes.c_void_p)]
+        lib.lasp_pool_create.restype = ctypes.c_int
+        lib.lasp_pool_load.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
+                                       ctypes.c_int32]
+        lib.lasp_pool_load.restype = ctypes.c_int
+        lib.lasp_pool_step.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        lib.lasp_pool_step.restype = ctypes.c_int
+        lib.lasp_pool_finish.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+        lib.lasp_pool_finish.restype = ctypes.c_int
+        lib.lasp_pool_destroy.argtypes = [vp]
+        lib.lasp_pool_destroy.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -192,9 +214,10 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
 
 
 def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False,
-            want_jac=False, margin=64, degree=10, precision="fp32", weight_quantile=0.5,
-            arms: Arms | None = None, box=None, stream=None) -> dict:
-    """lasp_forward: model, chi2, n_eff, gradient and model Jacobian at fixed u."""
+            want_jac=False, want_cov=False, margin=64, degree=10, precision="fp32",
+            weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None) -> dict:
+    """lasp_forward: model, chi2, J, n_eff, gradient, model Jacobian and
+    covariance at fixed normalised u."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
@@ -204,19 +227,22 @@ def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False
     grid = _grid(wave_grid, P)
     dev = obs.device
     res = dict(chi2=torch.empty(B, dtype=torch.float64, device=dev),
+               J=torch.empty(B, dtype=torch.float32, device=dev),
                n_eff=torch.empty(B, dtype=torch.int32, device=dev),
                status=torch.empty(B, dtype=torch.int32, device=dev))
     res["model"] = torch.empty((B, P), dtype=torch.float32, device=dev) if want_model else None
     res["grad"] = torch.empty((B, N_PAR), dtype=torch.float32, device=dev) if want_grad else None
     res["jac"] = torch.empty((B, N_PAR, P), dtype=torch.float32, device=dev) if want_jac else None
+    res["cov"] = (torch.empty((B, N_PAR, N_PAR), dtype=torch.float64, device=dev)
+                  if want_cov else None)
     o = make_opts(B, P, margin=margin, degree=degree, precision=precision,
                   weight_quantile=weight_quantile, arms=arms, box=box, stream=stream)
     o.status = ctypes.c_void_p(res["status"].data_ptr())
     with torch.cuda.device(dev):
         rc = lib.lasp_forward(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
                               _ptr(basis), _ptr(u), _ptr(res["model"]), _ptr(res["chi2"]),
-                              _ptr(res["n_eff"]), _ptr(res["grad"]), _ptr(res["jac"]),
-                              ctypes.byref(o))
+                              _ptr(res["J"]), _ptr(res["n_eff"]), _ptr(res["grad"]),
+                              _ptr(res["jac"]), _ptr(res["cov"]), ctypes.byref(o))
     _check(rc)
     return res
 
@@ -225,5 +251,74 @@ def release():
     load().lasp_release()
 
 
+def profile_enable(kernels=()):
+    """Time every later launch of the named kernel classes with HIP events."""
+    mask = 0
+    for k in kernels:
+        mask |= 1 << KERNELS.index(k)
+    _check(load().lasp_profile_enable(mask))
+
+
+def profile_read() -> dict:
+    """{kernel: (total_ms, launches)} since the last profile_enable()."""
+    n = len(KERNELS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(load().lasp_profile_read(ms, cnt, n))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
+
+
 DEFAULT_BOX = (np.array([math.log10(4000.0), 1.0, -2.5, -300.0, 50.0]),
                np.array([math.log10(8000.0), 5.0, 0.5, 300.0, 150.0]))
+
+
+class Pool:
+    """Resident fit slots of one spectral shape (lasp_pool_*), on one stream."""
+
+    def __init__(self, wave_grid, basis, capacity, *, margin=64, degree=10, precision="fp32",
+                 lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5,
+                 arms: Arms | None = None, box=None, stream=None):
+        lib = load()
+        P = int(np.asarray(wave_grid).shape[0])
+        _dev(basis, "basis", torch.float32, (N_BASIS, P + 2 * margin))
+        self.n_pix, self.capacity = P, int(capacity)
+        self.device = basis.device
+        self.stream = stream or torch.cuda.Stream(device=self.device)
+        self._grid = _grid(wave_grid, P)
+        self._opts = make_opts(capacity, P, margin=margin, degree=degree, precision=precision,
+                               lr=lr, betas=betas, eps=eps, weight_quantile=weight_quantile,
+                               arms=arms, box=box, stream=self.stream)
+        self.slot_bytes = int(lib.lasp_pool_slot_bytes(ctypes.byref(self._opts),
+                                                       self._grid.ctypes.data_as(ctypes.c_void_p)))
+        self._p = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.lasp_pool_create(self._grid.ctypes.data_as(ctypes.c_void_p), _ptr(basis),
+                                        ctypes.byref(self._opts), ctypes.byref(self._p)))
+
+    def load(self, slot0, obs, ivar, init_params, n_steps):
+        n = obs.shape[0]
+        _dev(obs, "obs", torch.float32, (n, self.n_pix))
+        _dev(ivar, "ivar", torch.float32, (n, self.n_pix))
+        _dev(init_params, "init_params", torch.float32, (n, N_PAR))
+        _check(load().lasp_pool_load(self._p, int(slot0), int(n), _ptr(obs), _ptr(ivar),
+                                     _ptr(init_params), int(n_steps)))
+
+    def step(self, slot_end, k):
+        _check(load().lasp_pool_step(self._p, int(slot_end), int(k)))
+
+    def finish(self, slot0, params, cov=None, status=None, chi2=None):
+        n = params.shape[0]
+        _dev(params, "params", torch.float32, (n, N_PAR))
+        _check(load().lasp_pool_finish(self._p, int(slot0), int(n), _ptr(params), _ptr(cov),
+                                       _ptr(status), _ptr(chi2)))
+
+    def close(self):
+        if self._p:
+            load().lasp_pool_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,6 +19,8 @@ from .generator import (  # noqa: F401
     SpectraBatch,
     make_basis,
     make_spectra,
+    make_spectra_parallel,
+    poisson_requests,
     shape_by_name,
     wave_grid,
 )

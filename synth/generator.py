@@ -275,3 +275,48 @@ def make_spectra(shape: Shape, lines: LineList, config_id: int, start: int, coun
             snr_all[k] = snr
             scale_all[k] = s
     return SpectraBatch(obs, ivar, init, truth, snr_all, scale_all)
+
+
+def _chunk(args):
+    shape, lines, config_id, start, count, init_mode, noise = args
+    return make_spectra(shape, lines, config_id, start, count, init_mode, noise)
+
+
+def make_spectra_parallel(shape: Shape, lines: LineList, config_id: int, start: int, count: int,
+                          init_mode: str = "perturbed", noise: bool = True,
+                          workers: int | None = None, chunk: int = 512) -> SpectraBatch:
+    """make_spectra split over worker processes (identical result: every item
+    has its own random stream).  Call before the process touches the GPU."""
+    import multiprocessing as mp
+    import os
+
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1 or count <= chunk:
+        return make_spectra(shape, lines, config_id, start, count, init_mode, noise)
+    jobs = [(shape, lines, config_id, s, min(chunk, start + count - s), init_mode, noise)
+            for s in range(start, start + count, chunk)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_chunk, jobs)
+    return SpectraBatch(*(np.concatenate([getattr(p, f.name) for p in parts])
+                          for f in dataclasses.fields(SpectraBatch)))
+
+
+def poisson_requests(spectra_per_s: float, duration_s: float, seed: int,
+                     lanes=("lamost3900", "desi7800"), weights=(0.5, 0.5),
+                     size_min: int = 1, size_max: int = 4096):
+    """Seeded request stream: exponential inter-arrival times at a request
+    rate that carries ``spectra_per_s`` on average, group sizes log-uniform
+    on [size_min, size_max], lanes drawn with ``weights``.  Returns a list of
+    (arrival time s, lane, size)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([5, seed])))
+    lo, hi = math.log(size_min), math.log(size_max + 1)
+    mean_size = (math.exp(hi) - math.exp(lo)) / (hi - lo)
+    rate = spectra_per_s / mean_size
+    out, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration_s:
+            return out
+        lane = lanes[int(rng.choice(len(lanes), p=np.asarray(weights) / np.sum(weights)))]
+        n = int(min(max(math.floor(math.exp(rng.uniform(lo, hi))), size_min), size_max))
+        out.append((t, lane, n))
