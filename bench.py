@@ -46,9 +46,11 @@ def parse(argv=None):
     p.add_argument("--sample-seconds", type=float, default=12.0,
                    help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--workload", choices=("grouped", "serving"), default="grouped",
+    p.add_argument("--workload", choices=("grouped", "serving", "copy"), default="grouped",
                    help="grouped: one 16,384-spectrum FP32 fit per step (default); serving: "
-                        "Poisson request stream over resident slot pools")
+                        "Poisson request stream over resident slot pools; copy: one plain "
+                        "device copy of --copy-mib MiB (calibrates HBM byte counters)")
+    p.add_argument("--copy-mib", type=int, default=1024)
     p.add_argument("--duration", type=float, default=20.0, help="serving: seconds of arrivals")
     p.add_argument("--rate", type=float, default=20000.0, help="serving: spectra/s offered")
     p.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32")
@@ -192,6 +194,17 @@ def main():
         sys.exit(2)
     if args.workload == "serving":
         return main_serving(args)
+    if args.workload == "copy":
+        import torch
+
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}))
+        return
 
     from synth import make_basis, make_spectra_parallel, shape_by_name, wave_grid
 

@@ -69,20 +69,20 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
   const bool multi = g.n_arms > 1;
 
   // ---- taps G, dG/dmu, dG/dsigma per arm ---------------------------------
-  const float u4 = s.u[(size_t)spec * kNP + 3];
-  const float u5 = s.u[(size_t)spec * kNP + 4];
-  const float rv = g.rv_lo + (u4 + 1.f) * g.rv_half;
-  const float sg = g.sg_lo + (u5 + 1.f) * g.sg_half;
-  const float mu = rv * g.inv_scale;
-  const float cmu = g.rv_half * g.inv_scale;
+  const double u4 = (double)s.u[(size_t)spec * kNP + 3];
+  const double u5 = (double)s.u[(size_t)spec * kNP + 4];
+  const double rv = g.rv_lo + (u4 + 1.0) * g.rv_half;
+  const double sg = g.sg_lo + (u5 + 1.0) * g.sg_half;
+  const double mu = rv * g.inv_scale;
+  const float cmu = (float)(g.rv_half * g.inv_scale);
   if (wave == 0) {
     for (int a = 0; a < g.n_arms; ++a) {
-      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
-      float spx = seff * g.inv_scale;
-      const bool fl = !(spx >= kSigmaFloorPx);
-      if (fl) spx = kSigmaFloorPx;
-      float hf = ceilf(fabsf(mu) + 5.f * spx);
-      if (!(hf <= (float)M)) hf = (float)M;
+      const double seff = g.bare ? sg : sqrt(sg * sg + g.arm_sig2[a]);
+      double spx = seff * g.inv_scale;
+      const bool fl = !(spx >= (double)kSigmaFloorPx);
+      if (fl) spx = (double)kSigmaFloorPx;
+      double hf = ceil(fabs(mu) + 5.0 * spx);
+      if (!(hf <= (double)M)) hf = (double)M;
       const int H = (int)hf, T = 2 * H + 1;
       double gv[3], dv[3];
       double part = 0.0;
@@ -91,8 +91,8 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
         const int idx = lane + 64 * k;
         double v = 0.0, d = 0.0;
         if (idx < T) {
-          d = (double)(idx - H) - (double)mu;
-          v = exp(-d * d / (2.0 * (double)spx * (double)spx));
+          d = (double)(idx - H) - mu;
+          v = exp(-d * d / (2.0 * spx * spx));
         }
         gv[k] = v;
         dv[k] = d;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
       }
       s1 = wave_sum(s1);
       s2 = wave_sum(s2);
-      const double sp = (double)spx;
+      const double sp = spx;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int idx = lane + 64 * k;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
       }
       if (lane == 0) {
         sHa[a] = H;
-        sCs[a] = fl ? 0.f : g.sg_half * g.inv_scale * (g.bare ? 1.f : sg / seff);
+        sCs[a] = fl ? 0.f : (float)(g.sg_half * g.inv_scale * (g.bare ? 1.0 : sg / seff));
       }
     }
   }

@@ -27,6 +27,7 @@ namespace {
 constexpr int kOffF = 16;  // F' column c lives at sF[kOffF + c]
 
 struct FusedLayout {
+  int rt_off;     // float offset of the per-wave transpose scratch [NW][kTB][64]
   int sf_len;     // floats
   int gb_off;     // float offset of the g-bar row (logical pixel j at gb_off + gb_base + j)
   int gb_base;    // 2M
@@ -41,15 +42,18 @@ struct FusedLayout {
 
 __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwaves, int nmom_pad) {
   FusedLayout L;
-  L.sf_len = kOffF + g.ldF + 32;
+  const int cols = g.ldF > kNPL * g.block ? g.ldF : kNPL * g.block;
+  L.sf_len = kOffF + cols + 32;
   L.gb_base = 2 * g.M;
   L.gb_len = g.P + 4 * g.M + 32;
+  if (L.gb_len < nwaves * 1024) L.gb_len = nwaves * 1024;  // also the moments' transpose scratch
   L.gb_off = (L.sf_len + 3) & ~3;
   L.ks = ((2 * g.M + 1 + 7) & ~7) + 8;
   L.k_off = (L.gb_off + L.gb_len + 3) & ~3;
   L.r_off = L.k_off + g.n_arms * L.ks;
   L.rs_off = L.r_off + nwaves * g.n_arms * L.ks;
-  int fl_end = L.rs_off + g.n_arms * L.ks;
+  L.rt_off = L.rs_off + g.n_arms * L.ks;
+  int fl_end = L.rt_off + nwaves * kTB * 64;
   L.d_off = ((fl_end * 4) + 15) & ~15;
   // doubles: reduction scratch [nwaves][64], moments [nmom_pad], b [32],
   // scalars [32] (flag, float b copy, per-arm H and sigma)
@@ -57,7 +61,7 @@ __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwave
   return L;
 }
 
-template <int BLOCK, int ND, bool ADJ>
+template <int BLOCK, int ND, bool ADJ, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *model_out) {
   constexpr int NW = BLOCK / 64;
   constexpr int NNU = 2 * ND - 1;  // nu_0 .. nu_{2D}
@@ -70,13 +74,14 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   float *sK = sF + L.k_off;
   float *sRp = sF + L.r_off;
   float *sRs = sF + L.rs_off;
+  float *sRt = sF + L.rt_off + (threadIdx.x >> 6) * (kTB * 64);
   double *sRed = reinterpret_cast<double *>(smem + L.d_off);
   double *sMom = sRed + NW * 64;
   double *sBd = sMom + NMOM;
   double *sScal = sBd + 32;
   float *sBf = reinterpret_cast<float *>(sScal + 8);  // [16]
   int *sHa = reinterpret_cast<int *>(sScal + 16);      // [kMaxArms]
-  float *sSp = reinterpret_cast<float *>(sScal + 20);  // [kMaxArms]
+  double *sSp = sScal + 24;                            // [kMaxArms]
 
   const int spec = blockIdx.x;
   if (ADJ && !slot_active(s, spec)) return;  // finished slot of a pool: no step
@@ -97,39 +102,39 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     for (int q = tid; q < NW * g.n_arms * L.ks; q += BLOCK) sRp[q] = 0.f;
   }
 
-  // ---- Eq. 5 kernel parameters: mu, sigma in pixels, H per arm ----------
-  const float u4 = s.u[(size_t)spec * kNP + 3];
-  const float u5 = s.u[(size_t)spec * kNP + 4];
-  const float rv = g.rv_lo + (u4 + 1.f) * g.rv_half;
-  const float sg = g.sg_lo + (u5 + 1.f) * g.sg_half;
-  const float mu = rv * g.inv_scale;
+  // ---- Eq. 5 kernel parameters: mu, sigma in pixels, H per arm (FP64) ----
+  const double u4 = (double)s.u[(size_t)spec * kNP + 3];
+  const double u5 = (double)s.u[(size_t)spec * kNP + 4];
+  const double rv = g.rv_lo + (u4 + 1.0) * g.rv_half;
+  const double sg = g.sg_lo + (u5 + 1.0) * g.sg_half;
+  const double mu = rv * g.inv_scale;
   if (wave == 0) {
     for (int a = 0; a < g.n_arms; ++a) {
-      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
-      float spx = seff * g.inv_scale;
-      if (!(spx >= kSigmaFloorPx)) spx = kSigmaFloorPx;
-      float hf = ceilf(fabsf(mu) + 5.f * spx);
-      if (!(hf <= (float)M)) hf = (float)M;  // also catches NaN
+      const double seff = g.bare ? sg : sqrt(sg * sg + g.arm_sig2[a]);
+      double spx = seff * g.inv_scale;
+      if (!(spx >= (double)kSigmaFloorPx)) spx = (double)kSigmaFloorPx;
+      double hf = ceil(fabs(mu) + 5.0 * spx);
+      if (!(hf <= (double)M)) hf = (double)M;  // also catches NaN
       const int H = (int)hf, T = 2 * H + 1;
-      const float inv2s2 = 0.5f / (spx * spx);
-      float gv[3];
-      float part = 0.f;
+      const double inv2s2 = 0.5 / (spx * spx);
+      double gv[3];
+      double part = 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int idx = lane + 64 * k;
-        float v = 0.f;
+        double v = 0.0;
         if (idx < T) {
-          const float d = (float)(idx - H) - mu;
-          v = expf(-d * d * inv2s2);
+          const double d = (double)(idx - H) - mu;
+          v = exp(-d * d * inv2s2);
         }
         gv[k] = v;
         part += v;
       }
-      const float inv_sum = 1.f / wave_sum(part);
+      const double inv_sum = 1.0 / wave_sum(part);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int idx = lane + 64 * k;
-        if (idx < L.ks) sK[a * L.ks + idx] = gv[k] * inv_sum;
+        if (idx < L.ks) sK[a * L.ks + idx] = (float)(gv[k] * inv_sum);
       }
       if (lane == 0) {
         sHa[a] = H;
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   __syncthreads();
 
   // ---- arms touched by this wave's output pixels (wave uniform) ---------
-  const bool multi = g.n_arms > 1;
+  constexpr bool multi = MULTI;  // several spectrograph arms
   const int wp0 = wave * 64 * kNPL;
   const int wp1 = min(wp0 + 64 * kNPL, P) - 1;
   int wa_lo = 0, wa_hi = 0;
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
           for (int i = 0; i < kNPL; ++i) acc[i] = fmaf(gk, w[i - t + kTB - 1], acc[i]);
         }
       }
-      if (!multi) {
+      if constexpr (!multi) {
 #pragma unroll
         for (int i = 0; i < kNPL; ++i) fpp[i] = acc[i];
       } else {
@@ -219,8 +224,14 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
         tm = tc;
         tc = tn;
       }
+      // one pixel at a time: keeps the scheduler from hoisting every pixel's
+      // FP64 operands (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
     }
-    block_sum_doubles<NW, NMOM>(acc, sRed, sMom, lane, wave);
+    // the g-bar row is not live yet: use it as transpose scratch, then clear it
+    block_sum_lds<NW, NMOM>(acc, reinterpret_cast<double *>(sF + L.gb_off), sRed, sMom, lane,
+                            wave);
+    for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
   }
 
   // ---- normal equations A b = r (A_mn = (nu_{m+n} + nu_|m-n|)/2), solved
@@ -292,8 +303,8 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       const float we = ow[i].y * e;
       chi2_part = fma((double)we, (double)e, chi2_part);
       gb[i] = ok ? -2.f * we * C * inv_neff : 0.f;
+      cmin = fminf(cmin, j < P ? C : INFINITY);
       if (j < P) {
-        cmin = fminf(cmin, C);
         if (model_out) model_out[(size_t)spec * P + j] = mdl * wsc;
         if (ADJ) sGb[j] = gb[i];
       }
@@ -320,8 +331,8 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     if (!ok) st |= kStSingular;
     if (!(cm > 0.0)) st |= kStContNonpos;
     for (int a = 0; a < g.n_arms; ++a) {
-      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
-      if (!(seff * g.inv_scale >= kSigmaFloorPx)) st |= kStSigmaFloor;
+      const double seff = g.bare ? sg : sqrt(sg * sg + g.arm_sig2[a]);
+      if (!(seff * g.inv_scale >= (double)kSigmaFloorPx)) st |= kStSigmaFloor;
     }
     s.status[spec] = st;
   }
@@ -332,7 +343,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     for (int a = wa_lo; a <= wa_hi; ++a) {
       const int H = sHa[a], T = 2 * H + 1;
       float gm[kNPL];
-      if (!multi) {
+      if constexpr (!multi) {
 #pragma unroll
         for (int i = 0; i < kNPL; ++i) gm[i] = has_pix ? gb[i] : 0.f;
       } else {
@@ -354,8 +365,26 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
           for (int i = 0; i < kNPL; ++i) acc = fmaf(gm[i], w[i - t + kTB - 1], acc);
           r[t] = acc;
         }
-        const float rs = wave_reduce_scatter<kTB, float>(r, lane);
-        if ((lane & 7) == 0) sRp[(wave * g.n_arms + a) * L.ks + mb + (lane >> 3)] = rs;
+        // wave-wide sums of the kTB partials: transpose through LDS, each
+        // group of 8 lanes adds one tap's 64 partials (fixed order)
+#pragma unroll
+        for (int t = 0; t < kTB; ++t) sRt[t * 64 + lane] = r[t];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        {
+          const int tt = lane >> 3, part = lane & 7;
+          const float4 x0 = *reinterpret_cast<const float4 *>(sRt + tt * 64 + 8 * part);
+          const float4 x1 = *reinterpret_cast<const float4 *>(sRt + tt * 64 + 8 * part + 4);
+          float v = ((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w));
+          v += __shfl_xor(v, 1, 64);
+          v += __shfl_xor(v, 2, 64);
+          v += __shfl_xor(v, 4, 64);
+          if (part == 0) sRp[(wave * g.n_arms + a) * L.ks + mb + tt] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
   }
@@ -375,7 +404,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       const int H = sHa[a], T = 2 * H + 1;
       double s1 = 0, s2 = 0, rg = 0, rgd = 0, rgd2 = 0;
       for (int idx = lane; idx < T; idx += 64) {
-        const double d = (double)(idx - H) - (double)mu;
+        const double d = (double)(idx - H) - mu;
         const double G = (double)sK[a * L.ks + idx];
         const double R = (double)sRs[a * L.ks + idx];
         s1 += G * d;
@@ -389,15 +418,13 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       rg = wave_sum(rg);
       rgd = wave_sum(rgd);
       rgd2 = wave_sum(rgd2);
-      const double sp = (double)sSp[a];
+      const double sp = sSp[a];
       const double dmu = (rgd - s1 * rg) / (sp * sp);
       const double dsig = (rgd2 - s2 * rg) / (sp * sp * sp);
-      g4 += dmu * (double)g.rv_half * (double)g.inv_scale;
-      const float seff = g.bare ? sg : sqrtf(sg * sg + g.arm_sig2[a]);
-      const bool fl = !(seff * g.inv_scale >= kSigmaFloorPx);
-      const double dsdu = fl ? 0.0
-                             : (double)g.sg_half * (double)g.inv_scale *
-                                   (g.bare ? 1.0 : (double)sg / (double)seff);
+      g4 += dmu * g.rv_half * g.inv_scale;
+      const double seff = g.bare ? sg : sqrt(sg * sg + g.arm_sig2[a]);
+      const bool fl = !(seff * g.inv_scale >= (double)kSigmaFloorPx);
+      const double dsdu = fl ? 0.0 : g.sg_half * g.inv_scale * (g.bare ? 1.0 : sg / seff);
       g5 += dsig * dsdu;
     }
     if (lane == 0) {
@@ -414,7 +441,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   if (c0 < g.Pe) {
     // arms whose pixels the columns of this wave can reach (wave uniform)
     int ta_lo = 0, ta_hi = 0;
-    if (multi) {
+    if constexpr (multi) {
       const int jlo = wave * 64 * kNPL - 2 * M;
       const int jhi = (wave + 1) * 64 * kNPL - 1;
       for (int a = 1; a < g.n_arms; ++a) {
@@ -432,7 +459,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
         float w[NWIN];
 #pragma unroll
         for (int q = 0; q < NWIN; ++q) w[q] = sGb[base + q];
-        if (multi) {
+        if constexpr (multi) {
 #pragma unroll
           for (int q = 0; q < NWIN; ++q) w[q] = (base + q >= lo && base + q < hi) ? w[q] : 0.f;
         }
@@ -447,8 +474,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   }
   __syncthreads();  // every read of F' in sF is done
 #pragma unroll
-  for (int i = 0; i < kNPL; ++i)
-    if (c0 + i < g.ldF) sF[kOffF + c0 + i] = (c0 + i < g.Pe) ? fb[i] : 0.f;
+  for (int i = 0; i < kNPL; ++i) sF[kOffF + c0 + i] = (c0 + i < g.Pe) ? fb[i] : 0.f;
   __syncthreads();
   {
     float4 *dst = reinterpret_cast<float4 *>(s.fbar + (size_t)spec * g.ldF);
@@ -457,24 +483,26 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   }
 }
 
+template <int BLOCK, int ND, bool ADJ, bool MULTI>
+hipError_t launch_fused_k(const Geometry &g, const State &s, float *model_out, hipStream_t st) {
+  const FusedLayout L = fused_layout(g, BLOCK / 64, 3 * ND - 1);
+  auto k = k_fused<BLOCK, ND, ADJ, MULTI>;
+  hipError_t e =
+      hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, model_out);
+  return hipGetLastError();
+}
+
 template <int BLOCK, int ND>
 hipError_t launch_fused_t(const Geometry &g, const State &s, int adjoint, float *model_out,
                           hipStream_t st) {
-  const FusedLayout L = fused_layout(g, BLOCK / 64, 3 * ND - 1);
-  if (adjoint) {
-    auto k = k_fused<BLOCK, ND, true>;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       L.bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, model_out);
-  } else {
-    auto k = k_fused<BLOCK, ND, false>;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       L.bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, model_out);
-  }
-  return hipGetLastError();
+  const bool multi = g.n_arms > 1;
+  if (adjoint)
+    return multi ? launch_fused_k<BLOCK, ND, true, true>(g, s, model_out, st)
+                 : launch_fused_k<BLOCK, ND, true, false>(g, s, model_out, st);
+  return multi ? launch_fused_k<BLOCK, ND, false, true>(g, s, model_out, st)
+               : launch_fused_k<BLOCK, ND, false, false>(g, s, model_out, st);
 }
 
 template <int BLOCK>

@@ -224,15 +224,15 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
       if (!(o->arm_sigma_kms[a] >= 0.f) || !isfinite(o->arm_sigma_kms[a]))
         return fail(LASP_E_ARG, "arm_sigma_kms must be finite and >= 0");
       g->arm_start[a] = o->arm_start[a];
-      g->arm_sig2[a] = o->arm_sigma_kms[a] * o->arm_sigma_kms[a];
+      g->arm_sig2[a] = (double)o->arm_sigma_kms[a] * (double)o->arm_sigma_kms[a];
     }
     g->arm_start[o->n_arms] = P;
   }
-  g->inv_scale = (float)(1.0 / (lasp::kCkms * lasp::kLn10 * dl));
-  g->rv_lo = (float)o->box_lo[3];
-  g->rv_half = (float)(0.5 * (o->box_hi[3] - o->box_lo[3]));
-  g->sg_lo = (float)o->box_lo[4];
-  g->sg_half = (float)(0.5 * (o->box_hi[4] - o->box_lo[4]));
+  g->inv_scale = 1.0 / (lasp::kCkms * lasp::kLn10 * dl);
+  g->rv_lo = o->box_lo[3];
+  g->rv_half = 0.5 * (o->box_hi[3] - o->box_lo[3]);
+  g->sg_lo = o->box_lo[4];
+  g->sg_half = 0.5 * (o->box_hi[4] - o->box_lo[4]);
   if (lasp::fused_smem_bytes(*g) > 160 * 1024)
     return fail(LASP_E_UNSUPPORTED, "shape needs more LDS than a workgroup has");
   return LASP_OK;

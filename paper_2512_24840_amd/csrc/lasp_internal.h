@@ -37,11 +37,11 @@ struct Geometry {
   int block;    // threads of the fused pass
   int n_arms;   // >= 1
   int arm_start[kMaxArms + 1];  // arm a covers pixels [arm_start[a], arm_start[a+1])
-  float arm_sig2[kMaxArms];     // instrumental sigma^2, (km/s)^2 (0 for a single bare arm)
+  double arm_sig2[kMaxArms];    // instrumental sigma^2, (km/s)^2 (0 for a single bare arm)
   int bare;                     // 1: one arm without instrument term
-  float inv_scale;              // pixels per km/s = 1 / (c ln10 dlog10)
-  float rv_lo, rv_half;         // RV = rv_lo + (u4 + 1) rv_half
-  float sg_lo, sg_half;         // sigma = sg_lo + (u5 + 1) sg_half
+  double inv_scale;             // pixels per km/s = 1 / (c ln10 dlog10)
+  double rv_lo, rv_half;        // RV = rv_lo + (u4 + 1) rv_half
+  double sg_lo, sg_half;        // sigma = sg_lo + (u5 + 1) sg_half
 };
 
 // Per-spectrum state and scratch owned by the library.
@@ -209,6 +209,47 @@ __device__ inline void block_sum_doubles(const double (&acc)[NV], double *red, d
     }
     __syncthreads();
   }
+}
+
+// Orders a wave's LDS accesses so that lanes see each other's stores.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum of NV per-lane doubles over the workgroup through LDS: eight values at
+// a time are transposed through scratch[wave][8][64] (one wave's region is
+// 4 KB), each group of eight lanes adds one value's 64 partials, then the
+// waves' results are added in a fixed order.  out[0..NV) is valid for every
+// thread after the call.  Deterministic.
+template <int NW, int NV>
+__device__ inline void block_sum_lds(const double (&acc)[NV], double *scratch, double *red,
+                                     double *out, int lane, int wave) {
+  double *sc = scratch + wave * 512;
+  const int tt = lane >> 3, part = lane & 7;
+#pragma unroll
+  for (int c = 0; c < (NV + 7) / 8; ++c) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) sc[t * 64 + lane] = (8 * c + t < NV) ? acc[(8 * c + t) % NV] : 0.0;
+    wave_lds_sync();
+    const double *row = sc + tt * 64 + 8 * part;
+    double v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    if (part == 0) red[wave * 64 + 8 * c + tt] = v;
+    wave_lds_sync();
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w * 64 + t];
+    out[t] = s;
+  }
+  __syncthreads();
 }
 
 #endif  // __HIPCC__
