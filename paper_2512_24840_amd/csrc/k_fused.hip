@@ -91,20 +91,35 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   const bool has_pix = j0 < P;
   const int jr = has_pix ? j0 : 0;     // window origin kept in range for idle lanes
 
-  // ---- stage F' into LDS, clear the g-bar row and the pads --------------
-  {
-    const float4 *src = reinterpret_cast<const float4 *>(s.fp + (size_t)spec * s.fp_stride);
-    for (int q = tid; q < g.ldF / 4; q += BLOCK)
-      *reinterpret_cast<float4 *>(sF + kOffF + 4 * q) = src[q];
-    for (int q = tid; q < kOffF; q += BLOCK) sF[q] = 0.f;
-    for (int q = tid; q < 32; q += BLOCK) sF[kOffF + g.ldF + q] = 0.f;
-    for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
-    for (int q = tid; q < NW * g.n_arms * L.ks; q += BLOCK) sRp[q] = 0.f;
-  }
-
-  // ---- Eq. 5 kernel parameters: mu, sigma in pixels, H per arm (FP64) ----
+  // ---- loads: the velocity and width first, then F' and the data, so that
+  //      the F' stores below need not wait for the data ---------------------
   const double u4 = (double)s.u[(size_t)spec * kNP + 3];
   const double u5 = (double)s.u[(size_t)spec * kNP + 4];
+  // 17 * BLOCK >= ldF, so every thread stages at most five float4 of F'.
+  constexpr int kStage = (kNPL * BLOCK / 4 + BLOCK - 1) / BLOCK;
+  const int n4 = g.ldF / 4;
+  float4 fst[kStage];
+  {
+    const float4 *src = reinterpret_cast<const float4 *>(s.fp + (size_t)spec * s.fp_stride);
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) fst[k] = src[min(tid + k * BLOCK, n4 - 1)];
+  }
+  float2 ow[kNPL];  // (o / w, W w^2), lane-major: coalesced
+  {
+    const float2 *src = s.ow + (size_t)spec * kNPL * BLOCK + tid;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) ow[i] = src[i * BLOCK];
+  }
+  // threads past the row store the last float4 again (the same value)
+#pragma unroll
+  for (int k = 0; k < kStage; ++k)
+    *reinterpret_cast<float4 *>(sF + kOffF + 4 * min(tid + k * BLOCK, n4 - 1)) = fst[k];
+  for (int q = tid; q < kOffF; q += BLOCK) sF[q] = 0.f;
+  for (int q = tid; q < 32; q += BLOCK) sF[kOffF + g.ldF + q] = 0.f;
+  for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
+  for (int q = tid; q < NW * g.n_arms * L.ks; q += BLOCK) sRp[q] = 0.f;
+
+  // ---- Eq. 5 kernel parameters: mu, sigma in pixels, H per arm (FP64) ----
   const double rv = g.rv_lo + (u4 + 1.0) * g.rv_half;
   const double sg = g.sg_lo + (u5 + 1.0) * g.sg_half;
   const double mu = rv * g.inv_scale;
@@ -123,7 +138,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       for (int k = 0; k < 3; ++k) {
         const int idx = lane + 64 * k;
         double v = 0.0;
-        if (idx < T) {
+        if (64 * k < T && idx < T) {  // first test is wave uniform
           const double d = (double)(idx - H) - mu;
           v = exp(-d * d * inv2s2);
         }
@@ -189,14 +204,6 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     }
   }
 
-  // ---- data (lane-major, coalesced); zero beyond P ------------------------
-  float2 ow[kNPL];
-  {
-    const float2 *src = s.ow + (size_t)spec * kNPL * BLOCK + tid;
-#pragma unroll
-    for (int i = 0; i < kNPL; ++i) ow[i] = src[i * BLOCK];
-  }
-
   // ---- Eq. 6 moments in FP64: nu_l = sum W F''^2 T_l, r_n = sum W F'' o T_n
   {
     double acc[NMOM];
@@ -250,7 +257,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     for (int k = 0; k < ND; ++k) {
       double piv[ND + 1];
 #pragma unroll
-      for (int n = k; n <= ND; ++n) piv[n] = __shfl(a[n], k, 64);
+      for (int n = k; n <= ND; ++n) piv[n] = read_lane(a[n], k);
       ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
       const double rp = 1.0 / piv[k];
       if (lane == k) {

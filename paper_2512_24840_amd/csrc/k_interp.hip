@@ -30,8 +30,9 @@ __device__ inline void feature_row(const float *u, int t, float *out) {
   } else {
     float d[3][kNB];
     feature_derivs(x, y, z, d);
+    // selects, not an indexed load: keeps d in registers
 #pragma unroll
-    for (int k = 0; k < kNB; ++k) out[k] = d[t - 1][k];
+    for (int k = 0; k < kNB; ++k) out[k] = t == 1 ? d[0][k] : (t == 2 ? d[1][k] : d[2][k]);
   }
 }
 
@@ -79,8 +80,35 @@ __global__ void k_split_basis(Geometry g, State s) {
   }
 }
 
+// Output staging of the forward contraction: a workgroup's 16 rows x 512
+// columns pass through LDS so that each row leaves as contiguous 1 KB runs
+// (the MFMA result layout alone gives 64-byte pieces of 16 rows).
+constexpr int kFwdCols = 4 * 16 * kFwdTiles;  // columns per workgroup
+constexpr int kFwdLd = kFwdCols + 4;           // LDS row stride (floats)
+
+__device__ inline void fwd_stage(float *sT, int wave, int lane, int n, const floatx4 &v) {
+  const int j = lane & 15, kq = lane >> 4;
+  *reinterpret_cast<float4 *>(sT + j * kFwdLd + wave * 16 * kFwdTiles + 16 * n + 4 * kq) =
+      make_float4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ inline void fwd_store(const Geometry &g, const State &s, const float *sT, int r0,
+                                 int rows) {
+  const int c_base = blockIdx.x * kFwdCols;
+#pragma unroll
+  for (int q = 0; q < 16 * kFwdCols / 4 / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int r = e / (kFwdCols / 4), c4 = e - r * (kFwdCols / 4);
+    const int col = c_base + 4 * c4;
+    if (r0 + r < rows && col < g.ldF)
+      *reinterpret_cast<float4 *>(s.fp + (size_t)(r0 + r) * g.ldF + col) =
+          *reinterpret_cast<const float4 *>(sT + r * kFwdLd + 4 * c4);
+  }
+}
+
 // BF16x3 variant of k_interp_fwd (same grid and output layout).
 __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, int rows_per_spec, int skip_done) {
+  __shared__ __align__(16) float sT[16 * kFwdLd];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rows = g.B * rows_per_spec;
   const int r0 = blockIdx.y * 16;
@@ -131,18 +159,19 @@ __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, in
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, b_hi, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_lo, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_hi, acc, 0, 0, 0);
-    if (my_row < rows) {
-      const float4 b0 = *reinterpret_cast<const float4 *>(s.basis + c0 + 4 * kq);
-      float4 *dst = reinterpret_cast<float4 *>(s.fp + (size_t)my_row * g.ldF + c0 + 4 * kq);
-      *dst = make_float4(fmaf(phi0, b0.x, acc[0]), fmaf(phi0, b0.y, acc[1]),
-                         fmaf(phi0, b0.z, acc[2]), fmaf(phi0, b0.w, acc[3]));
-    }
+    const float4 b0 = *reinterpret_cast<const float4 *>(s.basis + c0 + 4 * kq);
+    floatx4 out = {fmaf(phi0, b0.x, acc[0]), fmaf(phi0, b0.y, acc[1]), fmaf(phi0, b0.z, acc[2]),
+                   fmaf(phi0, b0.w, acc[3])};
+    fwd_stage(sT, wave, lane, n, out);
   }
+  __syncthreads();
+  fwd_store(g, s, sT, r0, rows);
 }
 
 // F'[r][c] = sum_k Phi[r][k] basis[k][c] for r < rows (rows = B or 4B with
 // derivative rows).  Grid: (ldF / (64 * kFwdTiles), ceil(rows / 16)).
 __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int rows_per_spec, int skip_done) {
+  __shared__ __align__(16) float sT[16 * kFwdLd];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rows = g.B * rows_per_spec;
   const int r0 = blockIdx.y * 16;
@@ -181,11 +210,10 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
       const float a = s.basis[(size_t)(4 * kk + kq) * g.ldF + c0 + (lane & 15)];
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[kk], acc, 0, 0, 0);
     }
-    if (my_row < rows) {
-      float4 *dst = reinterpret_cast<float4 *>(s.fp + (size_t)my_row * g.ldF + c0 + 4 * kq);
-      *dst = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    }
+    fwd_stage(sT, wave, lane, n, acc);
   }
+  __syncthreads();
+  fwd_store(g, s, sT, r0, rows);
 }
 
 // Phi-bar[s][k] = sum_c F-bar'[s][c] basis[k][c], then the gradient of
@@ -202,7 +230,7 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
   const int i_row = lane & 15;   // spectrum within the tile (A rows) / basis row (B cols)
   const int kq = lane >> 4;
   const bool row_ok = s0 + i_row < g.B;
-  const float *fb_row = s.fbar + (size_t)(s0 + i_row) * g.ldF;
+  const float *fb_row = s.fbar + (size_t)(row_ok ? s0 + i_row : s0) * g.ldF;
   const bool b1_ok = i_row < kNB - 16;
   const int b1 = 16 + (b1_ok ? i_row : 0);
   if (s.target) {  // the whole tile finished: nothing to do (uniform over the block)
@@ -212,27 +240,55 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
   }
 
   floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  const int per_wave = g.ldF / 4;  // ldF is a multiple of 64
+  const int per_wave = g.ldF / 4;  // ldF is a multiple of 128
   const int cb = wave * per_wave;
   const int ce = cb + per_wave;
   if (!BF16) {
     const float *b0_row = s.basis + (size_t)i_row * g.ldF;
     const float *b1_row = s.basis + (size_t)b1 * g.ldF;
-    for (int c = cb; c < ce; c += 16) {
+    // loads of kU column groups are issued before their products (more
+    // bytes in flight); rows past B and basis rows past 19 read a valid row
+    // and are zeroed
+    constexpr int kU = 8;
+    int c = cb;
+    for (; c + 16 * kU <= ce; c += 16 * kU) {
+      float4 fa[kU], bv0[kU], bv1[kU];
+#pragma unroll
+      for (int q = 0; q < kU; ++q) {
+        const int cc = c + 16 * q + 4 * kq;
+        fa[q] = *reinterpret_cast<const float4 *>(fb_row + cc);
+        bv0[q] = *reinterpret_cast<const float4 *>(b0_row + cc);
+        bv1[q] = *reinterpret_cast<const float4 *>(b1_row + cc);
+      }
+#pragma unroll
+      for (int q = 0; q < kU; ++q) {
+        const float4 a = row_ok ? fa[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 b = b1_ok ? bv1[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv0[q].x, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv0[q].y, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv0[q].z, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv0[q].w, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc1, 0, 0, 0);
+      }
+    }
+    for (; c < ce; c += 16) {
       const int cc = c + 4 * kq;
-      float4 fa = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row_ok) fa = *reinterpret_cast<const float4 *>(fb_row + cc);
+      float4 a = *reinterpret_cast<const float4 *>(fb_row + cc);
       const float4 bv0 = *reinterpret_cast<const float4 *>(b0_row + cc);
-      float4 bv1 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (b1_ok) bv1 = *reinterpret_cast<const float4 *>(b1_row + cc);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.x, bv0.x, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.x, bv1.x, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.y, bv0.y, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.y, bv1.y, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.z, bv0.z, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.z, bv1.z, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.w, bv0.w, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.w, bv1.w, acc1, 0, 0, 0);
+      float4 b = *reinterpret_cast<const float4 *>(b1_row + cc);
+      if (!row_ok) a = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!b1_ok) b = make_float4(0.f, 0.f, 0.f, 0.f);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv0.x, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv0.y, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv0.z, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv0.w, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc1, 0, 0, 0);
     }
   } else {
     const uint16_t *h0 = s.basis_hi + (size_t)i_row * g.ldF;

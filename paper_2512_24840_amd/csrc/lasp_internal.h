@@ -168,6 +168,14 @@ __device__ inline T wave_sum(T x) {
   return x;
 }
 
+// Value of v in lane l (l wave uniform), through scalar registers.
+__device__ inline double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline float wave_min(float x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
