@@ -82,6 +82,14 @@ def _load():
         lib.orc_fit.argtypes = [cp, fp, fp, fp, dp, ctypes.c_int, dp, dp, dp, ip, dp, dp, ip, up]
         lib.orc_fit.restype = ctypes.c_int
         lib.orc_covariance.argtypes = [cp, fp, fp, fp, dp, dp, dp]
+        lib.orc_stop_rule.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        lib.orc_stop_rule.restype = ctypes.c_int
+        lib.orc_stop_step.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ip]
+        lib.orc_stop_step.restype = ctypes.c_int
+        dd = ctypes.c_double
+        lib.orc_adam_fit.argtypes = [cp, fp, fp, fp, dp, ctypes.c_int, dd, dd, dd, dd,
+                                     ctypes.c_int, dd, dp, ip, ip, dp]
+        lib.orc_adam_fit.restype = ctypes.c_int
         lib.orc_covariance.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -235,6 +243,47 @@ def covariance(cfg: Config, obs, ivar, basis, u):
     rc = lib.orc_covariance(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u), _d(cov_u),
                             _d(cov_p))
     return dict(rc=rc, cov_u=cov_u, cov=cov_p)
+
+
+def stop_step(ell, n_max, window, tol):
+    """First step count at which stopping rule 2 or 3 holds on the loss
+    history ell (ell[t] after t steps), else n_max; returns (t, rule)."""
+    lib = _load()
+    ell = np.ascontiguousarray(ell, dtype=np.float64)
+    if ell.size < n_max:
+        raise ValueError("ell needs at least n_max entries")
+    rule = ctypes.c_int()
+    t = lib.orc_stop_step(_d(ell), int(n_max), int(window), float(tol), ctypes.byref(rule))
+    return t, rule.value
+
+
+def adam_fit(cfg: Config, obs, ivar, basis, u0, n_max=500, lr=1e-2, betas=(0.9, 0.999),
+             eps=1e-8, window=0, tol=1e-5):
+    """FP64 Adam on chi2/n_eff from normalised start u0, with the stopping
+    rules when window > 0.  Returns u, steps, rule, loss history, params."""
+    lib = _load()
+    obs, ivar, basis = _f32(obs), _f32(ivar), _f32(basis)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    u = np.empty(5)
+    ell = np.empty(n_max + 1)
+    steps = ctypes.c_int()
+    rule = ctypes.c_int()
+    lib.orc_adam_fit(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u0), int(n_max),
+                     float(lr), float(betas[0]), float(betas[1]), float(eps), int(window),
+                     float(tol), _d(u), ctypes.byref(steps), ctypes.byref(rule), _d(ell))
+    return dict(u=u, steps=steps.value, rule=rule.value, ell=ell[:steps.value + 1].copy(),
+                params=cfg.physical(u))
+
+
+def adam_fit_many(cfg: Config, obs, ivar, basis, init_phys, threads=None, **kw):
+    """adam_fit of each row on a thread pool; returns a list of dicts."""
+    n = obs.shape[0]
+    u0 = cfg.normalise(init_phys)
+    threads = threads or os.cpu_count() or 1
+    basis = _f32(basis)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(adam_fit, cfg, obs[i], ivar[i], basis, u0[i], **kw) for i in range(n)]
+        return [f.result() for f in futs]
 
 
 def fit_many(cfg: Config, obs, ivar, basis, init_phys, max_iter=200, threads=None):

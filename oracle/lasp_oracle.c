@@ -618,3 +618,86 @@ int orc_covariance(const orc_cfg *cfg, const float *obs, const float *ivar, cons
   work_free(&wk);
   return rc;
 }
+
+/*
+ * Stopping rules of the optimisation stage (Section 2.2, stage 8), for one
+ * spectrum.  ell[t] is the loss after t Adam steps (at the parameters the
+ * (t+1)-th step would start from).  The per-spectrum loss is the weighted
+ * RMS residual sqrt(chi2 / n_eff), the one-spectrum form of Eq. 9.
+ * After t steps the fit stops when
+ *   rule 2: t >= W and |ell[t-W] - ell[t]| < tol  (the loss changed by less
+ *           than tol over the last W steps), or
+ *   rule 3: t >= W and ell[s] > ell[s-1] for every s in t-W+1 .. t (the loss
+ *           rose at each of the last W steps);
+ * rule 1 stops it after n_max steps whatever the loss does.
+ * orc_stop_rule tests rules 2 and 3 at one t (ell[0..t] known) and returns
+ * 2, 3 or 0.  orc_stop_step scans t = 0 .. n_max - 1 and returns the first
+ * t at which rule 2 or 3 holds, with the rule in *rule; otherwise n_max
+ * with *rule = 1.  Rule 2 is tested first.
+ */
+int orc_stop_rule(const double *ell, int t, int W, double tol) {
+  if (W <= 0 || t < W) return 0;
+  if (fabs(ell[t - W] - ell[t]) < tol) return 2;
+  for (int q = t - W + 1; q <= t; ++q)
+    if (!(ell[q] > ell[q - 1])) return 0;
+  return 3;
+}
+
+int orc_stop_step(const double *ell, int n_max, int W, double tol, int *rule) {
+  for (int t = 0; t < n_max; ++t) {
+    int r = orc_stop_rule(ell, t, W, tol);
+    if (r) {
+      if (rule) *rule = r;
+      return t;
+    }
+  }
+  if (rule) *rule = 1;
+  return n_max;
+}
+
+/*
+ * The paper's optimiser for one spectrum: Adam (Kingma & Ba) on
+ * J = chi2 / n_eff over the normalised parameters u, each step using the
+ * gradient of orc_eval (continuum at its least-squares value), in the form
+ * of torch.optim.Adam with default settings other than lr: m and v are the
+ * first and second moment estimates, bias corrected with beta^t, and eps is
+ * added to the square root of the corrected v.  With W > 0 the stopping
+ * rules above end the fit (the step that would follow is not taken).
+ * Outputs: u_out[5], steps taken, rule (1, 2, 3), and optionally
+ * ell_out[0..steps] (n_max + 1 entries).  Returns 0.
+ */
+int orc_adam_fit(const orc_cfg *cfg, const float *obs, const float *ivar, const float *basis,
+                 const double *u0, int n_max, double lr, double beta1, double beta2, double eps,
+                 int W, double tol, double *u_out, int *steps_out, int *rule_out,
+                 double *ell_out) {
+  double u[ORC_NP], m[ORC_NP] = {0, 0, 0, 0, 0}, v[ORC_NP] = {0, 0, 0, 0, 0};
+  memcpy(u, u0, sizeof(u));
+  double *ell = (double *)malloc(sizeof(double) * (size_t)(n_max + 1));
+  int t = 0, rule = 1;
+  for (;; ++t) {
+    double chi2 = 0.0, g[ORC_NP];
+    int n_eff = 0;
+    orc_eval(cfg, obs, ivar, basis, u, NULL, NULL, NULL, NULL, &chi2, &n_eff, g, NULL, NULL);
+    ell[t] = n_eff > 0 ? sqrt(chi2 / (double)n_eff) : 0.0;
+    if (t == n_max) break;
+    int r = orc_stop_rule(ell, t, W, tol);
+    if (r) {
+      rule = r;
+      break;
+    }
+    const int step = t + 1;
+    const double bc1 = 1.0 - pow(beta1, (double)step);
+    const double bc2 = 1.0 - pow(beta2, (double)step);
+    for (int a = 0; a < ORC_NP; ++a) {
+      m[a] = beta1 * m[a] + (1.0 - beta1) * g[a];
+      v[a] = beta2 * v[a] + (1.0 - beta2) * g[a] * g[a];
+      u[a] -= lr * (m[a] / bc1) / (sqrt(v[a] / bc2) + eps);
+    }
+  }
+  memcpy(u_out, u, sizeof(u));
+  if (steps_out) *steps_out = t;
+  if (rule_out) *rule_out = rule;
+  if (ell_out) memcpy(ell_out, ell, sizeof(double) * (size_t)(t + 1));
+  free(ell);
+  return 0;
+}
