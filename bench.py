@@ -54,6 +54,12 @@ def parse(argv=None):
     p.add_argument("--duration", type=float, default=20.0, help="serving: seconds of arrivals")
     p.add_argument("--rate", type=float, default=20000.0, help="serving: spectra/s offered")
     p.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32")
+    p.add_argument("--serving-early-stop", action="store_true",
+                   help="serving: requests finish when their fits meet the stopping rules")
+    p.add_argument("--stop-window", type=int, default=50,
+                   help="window of the stopping rules in the early-stop leg")
+    p.add_argument("--stop-tol", type=float, default=1e-5,
+                   help="loss-change threshold of the stopping rules in the early-stop leg")
     return p.parse_args(argv)
 
 
@@ -97,7 +103,8 @@ def serving_banks(n_lamost=16384, n_desi=8192):
 
 
 def run_serving(banks, rate, duration, seed=0, n_steps=500, steps_per_tick=25,
-                capacity=(32768, 16384), precision="fp32", size_max=4096):
+                capacity=(32768, 16384), precision="fp32", size_max=4096, stop_window=0,
+                stop_tol=1e-5):
     """Serve a seeded Poisson stream of fit requests over one pool per shape.
     Returns (server, requests done, wall seconds, bank offsets per request)."""
     import torch
@@ -114,7 +121,7 @@ def run_serving(banks, rate, duration, seed=0, n_steps=500, steps_per_tick=25,
         arms = lasp.Arms(shape.arm_start, shape.arm_sigma_kms) if shape.arm_start else None
         pools[name] = lasp.Pool(wave_grid(shape), torch.from_numpy(basis).to(dev), cap,
                                 margin=shape.margin, degree=shape.degree, arms=arms,
-                                precision=precision)
+                                precision=precision, stop_window=stop_window, stop_tol=stop_tol)
     torch.cuda.synchronize()
     server = Server(pools, n_steps=n_steps, steps_per_tick=steps_per_tick)
     schedule = poisson_requests(rate, duration, seed, size_max=size_max)
@@ -143,9 +150,12 @@ def main_serving(args):
     banks = serving_banks()
     print("[bench] serving banks ready", file=sys.stderr, flush=True)
     # warm-up stream (kernel loading, pinned pools), then the measured one
-    run_serving(banks, args.rate, 1.0, seed=99, precision=args.precision)
+    sw = args.stop_window if args.serving_early_stop else 0
+    run_serving(banks, args.rate, 1.0, seed=99, precision=args.precision, stop_window=sw,
+                stop_tol=args.stop_tol)
     server, done, wall, where = run_serving(banks, args.rate, args.duration, seed=0,
-                                            precision=args.precision)
+                                            precision=args.precision, stop_window=sw,
+                                            stop_tol=args.stop_tol)
     lat = np.array([r.t_done - r.t_arrival for r in done]) * 1e3
     n_spec = sum(r.n for r in done)
     t_first = min(r.t_arrival for r in done)
@@ -158,8 +168,10 @@ def main_serving(args):
         else "bf16x3", "data": "synthetic",
         "config": {"workload": f"serving: Poisson stream {args.rate:.0f} spectra/s offered for "
                                f"{args.duration:.0f}s, LAMOST-like 3900 px / DESI-like 7800 px "
-                               "(3 arms) 50/50, group sizes log-uniform 1-4096, 500 Adam steps, "
-                               "continuous batching over resident slot pools",
+                               "(3 arms) 50/50, group sizes log-uniform 1-4096, 500 Adam steps"
+                               + (f" or the stopping rules (window {sw}, tol {args.stop_tol:g})"
+                                  if sw else "")
+                               + ", continuous batching over resident slot pools",
                    "requests": len(done), "ticks": server.ticks},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "unit": "ms from arrival to results on the host"},
@@ -259,6 +271,21 @@ def main():
     breakdown = lasp.profile_read()
     lasp.profile_enable([])
 
+    # the same group with the per-spectrum stopping rules of the optimisation
+    # stage (window 50, threshold 1e-5 on sqrt(chi2 / n_eff)), timed alone
+    es_kw = dict(kw, stop_window=args.stop_window, stop_tol=args.stop_tol)
+    res_es = lasp.fit_group(obs, ivar, grid, bas, init, args.adam_steps, **es_kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lasp.fit_group(obs, ivar, grid, bas, init, args.adam_steps, out=res_es, **es_kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_es = e0.elapsed_time(e1) / 1e3
+    steps_es = res_es.steps.cpu().numpy()
+    status_es = res_es.status.cpu().numpy()
+    params_es = res_es.params.cpu().numpy().astype(np.float64)
+
     params = res.params.cpu().numpy().astype(np.float64)
     status = res.status.cpu().numpy()
     flops_spec, T = fused_flops_per_spectrum(params, shape)
@@ -300,6 +327,15 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "status_flagged": int((status != 0).sum()),
+        "early_stop": {
+            "value": B / t_es, "unit": "spectra/s", "ms_per_group_fit": t_es * 1e3,
+            "window": args.stop_window, "tol": args.stop_tol, "max_steps": args.adam_steps,
+            "steps_mean": float(steps_es.mean()), "steps_p50": float(np.median(steps_es)),
+            "steps_p99": float(np.percentile(steps_es, 99)), "steps_max": int(steps_es.max()),
+            "stopped_flat": int(((status_es & lasp.ST_STOP_FLAT) != 0).sum()),
+            "stopped_rising": int(((status_es & lasp.ST_STOP_RISING) != 0).sum()),
+            "not_converged": int(((status_es & lasp.ST_NOT_CONVERGED) != 0).sum()),
+        },
     }
 
     if not args.no_cpu_baseline:
@@ -330,6 +366,11 @@ def main():
                                "max_abs_err": {k: float(v) for k, v in
                                                zip(("teff_K", "logg", "feh", "rv_kms"),
                                                    err.max(axis=0))}}
+        err_es = np.abs(params_es[:n] - refp)[:, :4]
+        out["early_stop"]["oracle_match"] = {
+            "n": n, "matched": int(np.all(err_es <= FIT_TOL, axis=1).sum()),
+            "max_abs_err": {k: float(v) for k, v in zip(("teff_K", "logg", "feh", "rv_kms"),
+                                                        err_es.max(axis=0))}}
     print(json.dumps(out), flush=True)
 
 

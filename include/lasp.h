@@ -56,6 +56,9 @@ extern "C" {
 #define LASP_ST_CONT_NONPOS 0x08u     /* fitted continuum P(x) b <= 0 at some pixel */
 #define LASP_ST_OUT_OF_BOX 0x10u      /* final |u_t| > 1.5 for some parameter */
 #define LASP_ST_SIGMA_FLOOR 0x20u     /* broadening width at the 0.1 px floor */
+#define LASP_ST_STOP_FLAT 0x40u       /* stopped: loss changed < stop_tol over the window */
+#define LASP_ST_STOP_RISING 0x80u     /* stopped: loss rose at every step of the window */
+#define LASP_ST_NOT_CONVERGED 0x100u  /* stopping rules on, step limit reached first */
 
 #define LASP_PREC_FP32 0   /* FP32 interpolator contraction */
 #define LASP_PREC_BF16X3 1 /* BF16 hi/lo split contraction, FP32 accumulate */
@@ -87,6 +90,16 @@ extern "C" {
  *  status          optional device uint32 [n_spec]: LASP_ST_* bits.
  *  out_chi2        optional device double [n_spec]: chi2 at the returned
  *                  parameters (weights ivar, data obs).
+ *  stop_window, stop_tol   per-spectrum stopping rules of Section 2.2 stage 8
+ *                  (0 = off: every fit takes n_steps steps).  With loss
+ *                  ell_t = sqrt(chi2 / n_eff) after t steps, a fit stops after
+ *                  t steps when t >= W and |ell_{t-W} - ell_t| < stop_tol
+ *                  (LASP_ST_STOP_FLAT), or when the loss rose at each of the
+ *                  last W steps (LASP_ST_STOP_RISING); otherwise after n_steps
+ *                  (LASP_ST_NOT_CONVERGED).  W = stop_window <= 4096; the
+ *                  paper's window is 50 and its threshold 1e-5.  A stopped
+ *                  fit takes no further steps; the others are not affected.
+ *  out_steps       optional device int32 [n_spec]: Adam steps each fit took.
  */
 typedef struct lasp_opts {
   int32_t n_spec;
@@ -105,12 +118,16 @@ typedef struct lasp_opts {
   void *stream;
   uint32_t *status;
   double *out_chi2;
+  int32_t stop_window;
+  float stop_tol;
+  int32_t *out_steps;
 } lasp_opts;
 
 /* Defaults: n_basis 20, margin 64, degree 10, FP32, box
  * lo = (log10 4000, 1, -2.5, -300, 50), hi = (log10 8000, 5, 0.5, 300, 150),
  * lr 1e-2, betas (0.9, 0.999), eps 1e-8, weight_quantile 0.5, no arms,
- * null stream, no status/chi2 outputs.  n_spec and n_pix are set to 0. */
+ * null stream, no status/chi2 outputs, stopping rules off (stop_window 0,
+ * stop_tol 1e-5), no out_steps.  n_spec and n_pix are set to 0. */
 void lasp_default_opts(lasp_opts *opts);
 
 /*
@@ -186,6 +203,12 @@ int lasp_profile_read(double *total_ms, int64_t *launches, int32_t n);
  *   lasp_pool_step        advances every slot in [0, slot_end) whose step
  *                         count is below its target by up to k Adam steps
  *                         (Section 2.2 stages 2-8); other slots are untouched.
+ *                         With opts->stop_window > 0 a slot also stops when a
+ *                         stopping rule holds (its target becomes its count).
+ *   lasp_pool_progress    writes, for slots [slot0, slot0 + count), the Adam
+ *                         steps taken (steps [count], device int32) and 1 if
+ *                         the slot has stopped, else 0 (done [count], device
+ *                         int32); either pointer may be NULL.
  *   lasp_pool_finish      evaluates slots [slot0, slot0 + count) at their
  *                         current parameters and writes out_params [count][5]
  *                         (physical units), optional out_cov [count][5][5],
@@ -201,6 +224,8 @@ int lasp_pool_create(const double *wave_grid, const float *basis, const lasp_opt
 int lasp_pool_load(lasp_pool *pool, int32_t slot0, int32_t count, const float *obs,
                    const float *ivar, const float *init_params, int32_t n_steps);
 int lasp_pool_step(lasp_pool *pool, int32_t slot_end, int32_t k);
+int lasp_pool_progress(lasp_pool *pool, int32_t slot0, int32_t count, int32_t *steps,
+                       int32_t *done);
 int lasp_pool_finish(lasp_pool *pool, int32_t slot0, int32_t count, float *out_params,
                      double *out_cov, uint32_t *status, double *chi2);
 int lasp_pool_destroy(lasp_pool *pool);

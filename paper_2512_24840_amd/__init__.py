@@ -11,6 +11,15 @@ from .lasp import (  # noqa: F401
     KERNELS,
     LaspError,
     Pool,
+    ST_CONT_NONPOS,
+    ST_NO_DATA,
+    ST_NONFINITE_INPUT,
+    ST_NOT_CONVERGED,
+    ST_OUT_OF_BOX,
+    ST_SIGMA_FLOOR,
+    ST_SINGULAR,
+    ST_STOP_FLAT,
+    ST_STOP_RISING,
     fit_group,
     forward,
     library_path,

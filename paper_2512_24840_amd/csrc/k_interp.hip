@@ -357,9 +357,34 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
 #pragma unroll
       for (int a = 0; a < kNP; ++a) grad_out[(size_t)spec * kNP + a] = grad[a];
     }
-    if (do_adam && slot_active(s, spec)) {
+    bool take = do_adam && slot_active(s, spec);
+    if (take && adam.stop_window > 0) {
+      // stopping rules of stage 8 on ell_t = sqrt(chi2 / n_eff) after t steps:
+      // a change below stop_tol over the last W steps, or a rise at each of
+      // them (the ring holds ell of the last W step counts)
+      const int t0 = s.t[spec], W = adam.stop_window;
+      const int n = s.neff[spec];
+      const double ell = n > 0 ? sqrt(s.chi2[spec] / (double)n) : 0.0;
+      double *h = s.lhist + (size_t)spec * W;
+      int rise = s.nrise[spec];
+      if (t0 >= 1) rise = ell > h[(t0 - 1) % W] ? rise + 1 : 0;
+      uint32_t bit = 0;
+      if (t0 >= W && fabs(h[t0 % W] - ell) < (double)adam.stop_tol)
+        bit = kStStopFlat;
+      else if (rise >= W)
+        bit = kStStopRising;
+      s.nrise[spec] = rise;
+      h[t0 % W] = ell;
+      if (bit) {
+        s.target[spec] = t0;
+        s.status[spec] |= bit;
+        take = false;
+      }
+    }
+    if (take) {
       const int step = s.t[spec] + 1;
       s.t[spec] = step;
+      if (adam.stop_window > 0 && step >= s.target[spec]) s.status[spec] |= kStNotConverged;
       const float bc1 = 1.f - powf(adam.beta1, (float)step);
       const float bc2 = 1.f - powf(adam.beta2, (float)step);
       const float step_size = adam.lr / bc1;
@@ -399,7 +424,7 @@ hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, 
 
 hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *adam,
                              float *grad_out, int bf16x3, hipStream_t st) {
-  AdamCfg a = adam ? *adam : AdamCfg{0.f, 0.f, 0.f, 0.f};
+  AdamCfg a = adam ? *adam : AdamCfg{0.f, 0.f, 0.f, 0.f, 0, 0.f};
   if (bf16x3)
     hipLaunchKernelGGL(k_interp_bwd<true>, dim3((g.B + 15) / 16), dim3(256), 0, st, g, s, a,
                        adam ? 1 : 0, grad_out);

@@ -150,6 +150,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
       }
       s.t[spec] = 0;
       if (s.target) s.target[spec] = target_steps;
+      if (s.nrise) s.nrise[spec] = 0;
     }
   }
 }
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
 __global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double blo2, double blo3,
                            double blo4, double bhi0, double bhi1, double bhi2, double bhi3,
                            double bhi4, float *out_params, uint32_t *status_out,
-                           double *chi2_out) {
+                           double *chi2_out, int32_t *steps_out) {
   const int spec = blockIdx.x * blockDim.x + threadIdx.x;
   if (spec >= g.B) return;
   const double lo[5] = {blo0, blo1, blo2, blo3, blo4};
@@ -174,6 +175,16 @@ __global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double
   s.status[spec] = st;
   if (status_out) status_out[spec] = st;
   if (chi2_out) chi2_out[spec] = s.chi2[spec];
+  if (steps_out) steps_out[spec] = s.t[spec];
+}
+
+// Steps taken and stopped flag of each slot.
+__global__ void k_progress(Geometry g, State s, int32_t *steps, int32_t *done) {
+  const int spec = blockIdx.x * blockDim.x + threadIdx.x;
+  if (spec >= g.B) return;
+  const int t = s.t[spec];
+  if (steps) steps[spec] = t;
+  if (done) done[spec] = (s.target && t >= s.target[spec]) ? 1 : 0;
 }
 
 // Per-spectrum results of a forward evaluation: chi2, the objective
@@ -212,11 +223,18 @@ hipError_t launch_prepare(const Geometry &g, const State &s, const float *obs, c
 
 hipError_t launch_finalize(const Geometry &g, const State &s, const double *lo, const double *hi,
                            float *out_params, uint32_t *status_out, double *chi2_out,
-                           hipStream_t st) {
+                           int32_t *steps_out, hipStream_t st) {
   const int bs = 256;
   hipLaunchKernelGGL(k_finalize, dim3((g.B + bs - 1) / bs), dim3(bs), 0, st, g, s, lo[0], lo[1],
                      lo[2], lo[3], lo[4], hi[0], hi[1], hi[2], hi[3], hi[4], out_params,
-                     status_out, chi2_out);
+                     status_out, chi2_out, steps_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_progress(const Geometry &g, const State &s, int32_t *steps, int32_t *done,
+                           hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_progress, dim3((g.B + bs - 1) / bs), dim3(bs), 0, st, g, s, steps, done);
   return hipGetLastError();
 }
 

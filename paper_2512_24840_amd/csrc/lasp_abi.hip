@@ -34,7 +34,7 @@ int dev_fail(hipError_t e, const char *where) {
 struct Workspace {
   int device = 0;
   hipStream_t stream = nullptr;
-  size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0;
+  size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0, cap_hist = 0;
   State s{};
 };
 
@@ -57,32 +57,36 @@ hipError_t grow(T *&p, size_t &cap, size_t need) {
 
 void free_ws(Workspace *w) {
   State &s = w->s;
-  void *ptrs[] = {s.u,    s.m,     s.v,        s.t,        s.ow,       s.wscale,   s.neff,
-                  s.status, s.fp,  s.fbar,     s.g45,      s.chi2,     s.basis,    s.basis_hi,
-                  s.basis_lo, s.basis_thi, s.basis_tlo};
+  void *ptrs[] = {s.u,        s.m,        s.v,        s.t,       s.target, s.nrise, s.lhist,
+                  s.ow,       s.wscale,   s.neff,     s.status,  s.fp,     s.fbar,  s.g45,
+                  s.chi2,     s.basis,    s.basis_hi, s.basis_lo, s.basis_thi, s.basis_tlo};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   w->s = State{};
-  w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = 0;
+  w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = w->cap_hist = 0;
 }
 
 // Grows the buffers of w to hold g.B spectra of geometry g (fp_rows rows of F'
-// per spectrum).  Earlier work on the stream may still use old buffers, so
-// the stream is synchronised before anything is freed.
-int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, hipStream_t st) {
+// per spectrum, a loss history of hist_w entries when the stopping rules are
+// on).  Earlier work on the stream may still use old buffers, so the stream
+// is synchronised before anything is freed.
+int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hipStream_t st) {
   const size_t B = (size_t)g.B;
+  const size_t need_hist = B * (size_t)hist_w;
   const size_t need_ow = B * lasp::kNPL * g.block;
   const size_t need_fp = B * fp_rows * g.ldF;
   const size_t need_fbar = B * g.ldF;
   const size_t need_basis = (size_t)lasp::kNB * g.ldF;
   const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
-                      need_fbar > w->cap_fbar || need_basis > w->cap_basis || !w->s.u;
+                      need_fbar > w->cap_fbar || need_basis > w->cap_basis ||
+                      need_hist > w->cap_hist || !w->s.u;
   if (!regrow) return LASP_OK;
   hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
   State &s = w->s;
   const size_t cb = w->cap_B;
   size_t c1 = cb, c2 = cb, c3 = cb, c4 = cb, c5 = cb, c6 = cb, c7 = cb, c8 = cb, c9 = cb;
+  size_t c10 = cb, c11 = cb;
   hipError_t r = hipSuccess;
   if (B > cb || !s.u) {
     r = grow(s.u, c1, B * lasp::kNP);
@@ -94,8 +98,11 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, hipStream_t st)
     if (r == hipSuccess) r = grow(s.status, c7, B);
     if (r == hipSuccess) r = grow(s.g45, c8, B * 2);
     if (r == hipSuccess) r = grow(s.chi2, c9, B);
+    if (r == hipSuccess) r = grow(s.target, c10, B);
+    if (r == hipSuccess) r = grow(s.nrise, c11, B);
     if (r == hipSuccess) w->cap_B = B;
   }
+  if (r == hipSuccess && need_hist > 0) r = grow(s.lhist, w->cap_hist, need_hist);
   if (r == hipSuccess) r = grow(s.ow, w->cap_ow, need_ow);
   if (r == hipSuccess) r = grow(s.fp, w->cap_fp, need_fp);
   if (r == hipSuccess) r = grow(s.fbar, w->cap_fbar, need_fbar);
@@ -119,7 +126,7 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, hipStream_t st)
   return LASP_OK;
 }
 
-int get_workspace(const Geometry &g, int fp_rows, hipStream_t st, Workspace **out) {
+int get_workspace(const Geometry &g, int fp_rows, int hist_w, hipStream_t st, Workspace **out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
@@ -132,14 +139,14 @@ int get_workspace(const Geometry &g, int fp_rows, hipStream_t st, Workspace **ou
     w->stream = st;
     g_ws[key] = w;
   }
-  int rc = ensure_buffers(w, g, fp_rows, st);
+  int rc = ensure_buffers(w, g, fp_rows, hist_w, st);
   if (rc) return rc;
   *out = w;
   return LASP_OK;
 }
 
 // Per-spectrum pointers shifted to start at slot0 (fp_rows rows of F' each).
-State offset_state(const State &s, const Geometry &g, int slot0, int fp_rows) {
+State offset_state(const State &s, const Geometry &g, int slot0, int fp_rows, int hist_w) {
   State o = s;
   const size_t k = (size_t)slot0;
   o.u += k * lasp::kNP;
@@ -147,6 +154,8 @@ State offset_state(const State &s, const Geometry &g, int slot0, int fp_rows) {
   o.v += k * lasp::kNP;
   o.t += k;
   if (o.target) o.target += k;
+  if (o.nrise) o.nrise += k;
+  if (o.lhist) o.lhist += k * (size_t)hist_w;
   o.ow += k * lasp::kNPL * g.block;
   o.wscale += k;
   o.neff += k;
@@ -176,6 +185,10 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
       !(o->eps > 0.f))
     return fail(LASP_E_ARG, "invalid Adam hyper-parameters");
   if (o->n_arms < 0 || o->n_arms > LASP_MAX_ARMS) return fail(LASP_E_ARG, "n_arms must be 0..4");
+  if (o->stop_window < 0 || o->stop_window > lasp::kMaxStopWindow)
+    return fail(LASP_E_ARG, "stop_window must be in [0, 4096]");
+  if (!(o->stop_tol >= 0.f) || !std::isfinite(o->stop_tol))
+    return fail(LASP_E_ARG, "stop_tol must be finite and >= 0");
   if (!wave_grid) return fail(LASP_E_ARG, "wave_grid is NULL");
 
   const int P = o->n_pix;
@@ -339,6 +352,8 @@ void lasp_default_opts(lasp_opts *o) {
   o->beta2 = 0.999f;
   o->eps = 1e-8f;
   o->weight_quantile = 0.5f;
+  o->stop_window = 0;
+  o->stop_tol = 1e-5f;
 }
 
 const char *lasp_last_error(void) { return g_err.c_str(); }
@@ -392,9 +407,11 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   if (g.B == 0) return LASP_OK;
   hipStream_t st = (hipStream_t)opts->stream;
   Workspace *w = nullptr;
-  rc = get_workspace(g, out_cov ? 4 : 1, st, &w);
+  const int W = opts->stop_window;
+  rc = get_workspace(g, out_cov ? 4 : 1, W, st, &w);
   if (rc) return rc;
   State s = w->s;
+  if (W == 0) s.target = nullptr;  // every spectrum takes n_steps steps
   const int bf16 = opts->precision == LASP_PREC_BF16X3;
   rc = copy_basis(g, s, basis, bf16, st);
   if (rc) return rc;
@@ -404,7 +421,7 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
                                     opts->weight_quantile, 1, n_steps, st),
                "prepare");
   }
-  const lasp::AdamCfg adam{opts->lr, opts->beta1, opts->beta2, opts->eps};
+  const lasp::AdamCfg adam{opts->lr, opts->beta1, opts->beta2, opts->eps, W, opts->stop_tol};
   s.fp_stride = g.ldF;
   for (int it = 0; it < n_steps; ++it) {
     {
@@ -420,7 +437,9 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
       LASP_CHECK(lasp::launch_interp_bwd(g, s, &adam, nullptr, bf16, st), "adjoint contraction + Adam");
     }
   }
-  // chi2 and status at the returned parameters; derivative rows for the covariance
+  // chi2 and status at the returned parameters (every spectrum, stopped or
+  // not); derivative rows for the covariance
+  s.target = nullptr;
   s.fp_stride = out_cov ? 4 * g.ldF : g.ldF;
   LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, bf16, st), "interpolator contraction");
   LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, st), "fused pass");
@@ -432,7 +451,7 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   {
     LASP_TIMED(LASP_K_FINALIZE, st);
     LASP_CHECK(lasp::launch_finalize(g, s, opts->box_lo, opts->box_hi, out_params, opts->status,
-                                     opts->out_chi2, st),
+                                     opts->out_chi2, opts->out_steps, st),
                "finalize");
   }
   return LASP_OK;
@@ -452,9 +471,10 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid, c
   hipStream_t st = (hipStream_t)opts->stream;
   const bool rows4 = out_jac || out_cov;
   Workspace *w = nullptr;
-  rc = get_workspace(g, rows4 ? 4 : 1, st, &w);
+  rc = get_workspace(g, rows4 ? 4 : 1, 0, st, &w);
   if (rc) return rc;
   State s = w->s;
+  s.target = nullptr;
   const int bf16 = opts->precision == LASP_PREC_BF16X3;
   rc = copy_basis(g, s, basis, bf16, st);
   if (rc) return rc;
@@ -499,7 +519,6 @@ struct lasp_pool {
   int device;
   int bf16;
   Workspace w;
-  int *target;
 };
 
 namespace {
@@ -515,7 +534,8 @@ extern "C" {
 size_t lasp_pool_slot_bytes(const lasp_opts *opts, const double *wave_grid) {
   Geometry g;
   if (make_geometry(opts, wave_grid, &g)) return 0;
-  return (size_t)lasp::kNPL * g.block * 8 + (size_t)5 * g.ldF * 4 + 64 + 3 * 20 + 40;
+  return (size_t)lasp::kNPL * g.block * 8 + (size_t)5 * g.ldF * 4 + 64 + 3 * 20 + 48 +
+         (size_t)8 * opts->stop_window;
 }
 
 int lasp_pool_create(const double *wave_grid, const float *basis, const lasp_opts *opts,
@@ -533,20 +553,14 @@ int lasp_pool_create(const double *wave_grid, const float *basis, const lasp_opt
   p->opts = *opts;
   p->st = (hipStream_t)opts->stream;
   p->bf16 = opts->precision == LASP_PREC_BF16X3;
-  p->target = nullptr;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
     return dev_fail(e, "hipGetDevice");
   }
-  rc = ensure_buffers(&p->w, g, 4, p->st);
+  rc = ensure_buffers(&p->w, g, 4, opts->stop_window, p->st);
   if (!rc) {
-    e = hipMalloc((void **)&p->target, sizeof(int) * g.B);
-    if (e != hipSuccess) rc = fail(LASP_E_NOMEM, "pool target array");
-  }
-  if (!rc) {
-    p->w.s.target = p->target;
-    e = hipMemsetAsync(p->target, 0, sizeof(int) * g.B, p->st);
+    e = hipMemsetAsync(p->w.s.target, 0, sizeof(int) * g.B, p->st);
     if (e == hipSuccess) e = hipMemsetAsync(p->w.s.t, 0, sizeof(int) * g.B, p->st);
     if (e != hipSuccess) rc = dev_fail(e, "pool init");
   }
@@ -567,7 +581,7 @@ int lasp_pool_load(lasp_pool *p, int32_t slot0, int32_t count, const float *obs,
     return fail(LASP_E_ARG, "slot range outside the pool or n_steps < 0");
   Geometry g;
   pool_geometry(p, count, &g);
-  State s = offset_state(p->w.s, p->g, slot0, 4);
+  State s = offset_state(p->w.s, p->g, slot0, 4, p->opts.stop_window);
   LASP_TIMED(LASP_K_PREPARE, p->st);
   LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, init_params, p->opts.box_lo, p->opts.box_hi,
                                   p->opts.weight_quantile, 1, n_steps, p->st),
@@ -584,7 +598,8 @@ int lasp_pool_step(lasp_pool *p, int32_t slot_end, int32_t k) {
   pool_geometry(p, slot_end, &g);
   State s = p->w.s;
   s.fp_stride = g.ldF;
-  const lasp::AdamCfg adam{p->opts.lr, p->opts.beta1, p->opts.beta2, p->opts.eps};
+  const lasp::AdamCfg adam{p->opts.lr,  p->opts.beta1,       p->opts.beta2,
+                           p->opts.eps, p->opts.stop_window, p->opts.stop_tol};
   for (int it = 0; it < k; ++it) {
     {
       LASP_TIMED(LASP_K_INTERP_FWD, p->st);
@@ -603,6 +618,20 @@ int lasp_pool_step(lasp_pool *p, int32_t slot_end, int32_t k) {
   return LASP_OK;
 }
 
+int lasp_pool_progress(lasp_pool *p, int32_t slot0, int32_t count, int32_t *steps,
+                       int32_t *done) {
+  g_err.clear();
+  if (!p) return fail(LASP_E_ARG, "pool is NULL");
+  if (slot0 < 0 || count < 1 || slot0 + count > p->g.B)
+    return fail(LASP_E_ARG, "slot range outside the pool");
+  if (!steps && !done) return LASP_OK;
+  Geometry g;
+  pool_geometry(p, count, &g);
+  State s = offset_state(p->w.s, p->g, slot0, 4, p->opts.stop_window);
+  LASP_CHECK(lasp::launch_progress(g, s, steps, done, p->st), "progress");
+  return LASP_OK;
+}
+
 int lasp_pool_finish(lasp_pool *p, int32_t slot0, int32_t count, float *out_params,
                      double *out_cov, uint32_t *status, double *chi2) {
   g_err.clear();
@@ -612,7 +641,7 @@ int lasp_pool_finish(lasp_pool *p, int32_t slot0, int32_t count, float *out_para
   Geometry g;
   pool_geometry(p, count, &g);
   const int rows = out_cov ? 4 : 1;
-  State s = offset_state(p->w.s, p->g, slot0, rows);
+  State s = offset_state(p->w.s, p->g, slot0, rows, p->opts.stop_window);
   s.target = nullptr;  // the final evaluation covers every slot of the range
   s.fp_stride = rows * g.ldF;
   LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, p->bf16, p->st),
@@ -625,7 +654,7 @@ int lasp_pool_finish(lasp_pool *p, int32_t slot0, int32_t count, float *out_para
   }
   LASP_TIMED(LASP_K_FINALIZE, p->st);
   LASP_CHECK(lasp::launch_finalize(g, s, p->opts.box_lo, p->opts.box_hi, out_params, status,
-                                   chi2, p->st),
+                                   chi2, nullptr, p->st),
              "finalize");
   return LASP_OK;
 }
@@ -634,7 +663,6 @@ int lasp_pool_destroy(lasp_pool *p) {
   if (!p) return LASP_OK;
   (void)hipStreamSynchronize(p->st);
   free_ws(&p->w);
-  if (p->target) (void)hipFree(p->target);
   delete p;
   return LASP_OK;
 }

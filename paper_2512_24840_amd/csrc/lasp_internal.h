@@ -23,6 +23,10 @@ constexpr uint32_t kStSingular = 0x04u;
 constexpr uint32_t kStContNonpos = 0x08u;
 constexpr uint32_t kStOutOfBox = 0x10u;
 constexpr uint32_t kStSigmaFloor = 0x20u;
+constexpr uint32_t kStStopFlat = 0x40u;
+constexpr uint32_t kStStopRising = 0x80u;
+constexpr uint32_t kStNotConverged = 0x100u;
+constexpr int kMaxStopWindow = 4096;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -60,6 +64,8 @@ struct State {
   float *fbar;      // [B][ldF] F-bar'
   float *g45;       // [B][2] dJ/du4, dJ/du5
   double *chi2;     // [B]
+  double *lhist;    // [B][stop window] loss history ring (stopping rules)
+  int *nrise;       // [B] consecutive steps at which the loss rose
   float *basis;     // [20][ldF] zero-padded copy of the basis
   uint16_t *basis_hi;  // [20][ldF] bf16 high part (BF16x3, adjoint contraction)
   uint16_t *basis_lo;  // [20][ldF] bf16 low part
@@ -69,6 +75,8 @@ struct State {
 
 struct AdamCfg {
   float lr, beta1, beta2, eps;
+  int stop_window;  // 0: fixed step count
+  float stop_tol;
 };
 
 // ---------------------------------------------------------------- host side
@@ -91,7 +99,9 @@ hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *a
 hipError_t launch_split_basis(const Geometry &g, const State &s, hipStream_t st);
 hipError_t launch_finalize(const Geometry &g, const State &s, const double *box_lo,
                            const double *box_hi, float *out_params, uint32_t *status_out,
-                           double *chi2_out, hipStream_t st);
+                           double *chi2_out, int32_t *steps_out, hipStream_t st);
+hipError_t launch_progress(const Geometry &g, const State &s, int32_t *steps, int32_t *done,
+                           hipStream_t st);
 hipError_t launch_cov(const Geometry &g, const State &s, const double *box_lo, const double *box_hi,
                       double *out_cov, float *out_jac, hipStream_t st);
 hipError_t launch_outputs(const Geometry &g, const State &s, double *chi2_out, float *J_out,

@@ -27,13 +27,16 @@ ST_SINGULAR = 0x04
 ST_CONT_NONPOS = 0x08
 ST_OUT_OF_BOX = 0x10
 ST_SIGMA_FLOOR = 0x20
+ST_STOP_FLAT = 0x40
+ST_STOP_RISING = 0x80
+ST_NOT_CONVERGED = 0x100
 PREC = {"fp32": 0, "bf16x3": 1}
 N_BASIS = 20
 N_PAR = 5
 EXPORTED = ("lasp_default_opts", "lasp_fit_group", "lasp_forward", "lasp_last_error",
             "lasp_release", "lasp_profile_enable", "lasp_profile_read", "lasp_pool_slot_bytes",
-            "lasp_pool_create", "lasp_pool_load", "lasp_pool_step", "lasp_pool_finish",
-            "lasp_pool_destroy")
+            "lasp_pool_create", "lasp_pool_load", "lasp_pool_step", "lasp_pool_progress",
+            "lasp_pool_finish", "lasp_pool_destroy")
 KERNELS = ("prepare", "interp_fwd", "fused", "interp_bwd", "cov", "finalize")
 
 
@@ -64,6 +67,9 @@ class LaspOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
         ("out_chi2", ctypes.c_void_p),
+        ("stop_window", ctypes.c_int32),
+        ("stop_tol", ctypes.c_float),
+        ("out_steps", ctypes.c_void_p),
     ]
 
 
@@ -109,6 +115,8 @@ def load() -> ctypes.CDLL:
         lib.lasp_pool_load.restype = ctypes.c_int
         lib.lasp_pool_step.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         lib.lasp_pool_step.restype = ctypes.c_int
+        lib.lasp_pool_progress.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+        lib.lasp_pool_progress.restype = ctypes.c_int
         lib.lasp_pool_finish.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         lib.lasp_pool_finish.restype = ctypes.c_int
         lib.lasp_pool_destroy.argtypes = [vp]
@@ -146,13 +154,14 @@ class Arms:
 
 def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
               betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5, arms: Arms | None = None,
-              box=None, stream=None) -> LaspOpts:
+              box=None, stream=None, stop_window=0, stop_tol=1e-5) -> LaspOpts:
     o = LaspOpts()
     load().lasp_default_opts(ctypes.byref(o))
     o.n_spec, o.n_pix, o.margin, o.degree = int(n_spec), int(n_pix), int(margin), int(degree)
     o.precision = PREC[precision]
     o.lr, o.beta1, o.beta2, o.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
     o.weight_quantile = float(weight_quantile)
+    o.stop_window, o.stop_tol = int(stop_window), float(stop_tol)
     if box is not None:
         lo, hi = box
         for t in range(5):
@@ -180,13 +189,15 @@ class FitResult:
     cov: torch.Tensor | None      # [B, 5, 5] float64, physical units
     status: torch.Tensor          # [B] int32 (LASP_ST_* bits)
     chi2: torch.Tensor            # [B] float64
+    steps: torch.Tensor | None = None  # [B] int32 Adam steps taken
 
 
 def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=False,
               margin=64, degree=10, precision="fp32", lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
               weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
-              out: FitResult | None = None) -> FitResult:
-    """lasp_fit_group on device tensors; returns after enqueueing (stream ordered)."""
+              stop_window=0, stop_tol=1e-5, out: FitResult | None = None) -> FitResult:
+    """lasp_fit_group on device tensors; returns after enqueueing (stream ordered).
+    stop_window > 0 turns on the per-spectrum stopping rules (window, stop_tol)."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
@@ -200,11 +211,15 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
                         torch.empty((B, N_PAR, N_PAR), dtype=torch.float64, device=dev)
                         if want_cov else None,
                         torch.empty(B, dtype=torch.int32, device=dev),
-                        torch.empty(B, dtype=torch.float64, device=dev))
+                        torch.empty(B, dtype=torch.float64, device=dev),
+                        torch.empty(B, dtype=torch.int32, device=dev))
     o = make_opts(B, P, margin=margin, degree=degree, precision=precision, lr=lr, betas=betas,
-                  eps=eps, weight_quantile=weight_quantile, arms=arms, box=box, stream=stream)
+                  eps=eps, weight_quantile=weight_quantile, arms=arms, box=box, stream=stream,
+                  stop_window=stop_window, stop_tol=stop_tol)
     o.status = ctypes.c_void_p(out.status.data_ptr())
     o.out_chi2 = ctypes.c_void_p(out.chi2.data_ptr())
+    if out.steps is not None:
+        o.out_steps = ctypes.c_void_p(out.steps.data_ptr())
     with torch.cuda.device(dev):
         rc = lib.lasp_fit_group(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
                                 _ptr(basis), _ptr(init_params), _ptr(out.params), _ptr(out.cov),
@@ -277,7 +292,7 @@ class Pool:
 
     def __init__(self, wave_grid, basis, capacity, *, margin=64, degree=10, precision="fp32",
                  lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5,
-                 arms: Arms | None = None, box=None, stream=None):
+                 arms: Arms | None = None, box=None, stream=None, stop_window=0, stop_tol=1e-5):
         lib = load()
         P = int(np.asarray(wave_grid).shape[0])
         _dev(basis, "basis", torch.float32, (N_BASIS, P + 2 * margin))
@@ -287,7 +302,9 @@ class Pool:
         self._grid = _grid(wave_grid, P)
         self._opts = make_opts(capacity, P, margin=margin, degree=degree, precision=precision,
                                lr=lr, betas=betas, eps=eps, weight_quantile=weight_quantile,
-                               arms=arms, box=box, stream=self.stream)
+                               arms=arms, box=box, stream=self.stream, stop_window=stop_window,
+                               stop_tol=stop_tol)
+        self.stop_window = int(stop_window)
         self.slot_bytes = int(lib.lasp_pool_slot_bytes(ctypes.byref(self._opts),
                                                        self._grid.ctypes.data_as(ctypes.c_void_p)))
         self._p = ctypes.c_void_p()
@@ -305,6 +322,18 @@ class Pool:
 
     def step(self, slot_end, k):
         _check(load().lasp_pool_step(self._p, int(slot_end), int(k)))
+
+    def progress(self, slot0, steps=None, done=None):
+        """Steps taken and stopped flags of slots [slot0, slot0 + n) into
+        int32 device tensors of length n (stream ordered)."""
+        t = steps if steps is not None else done
+        if t is None:
+            return
+        n = t.shape[0]
+        for x, nm in ((steps, "steps"), (done, "done")):
+            if x is not None:
+                _dev(x, nm, torch.int32, (n,))
+        _check(load().lasp_pool_progress(self._p, int(slot0), int(n), _ptr(steps), _ptr(done)))
 
     def finish(self, slot0, params, cov=None, status=None, chi2=None):
         n = params.shape[0]

@@ -8,7 +8,11 @@ starts at step 0), and then advances together with every other resident fit
 each tick (k Adam steps per tick, one launch sequence per shape, the shapes'
 streams overlapping on the device).  When a request has taken its n_steps,
 its slots are evaluated, the results are copied to pinned host memory and,
-once that copy has completed, the slots are freed for queued requests.
+once that copy has completed, the slots are freed for queued requests.  With
+the stopping rules on (a pool created with stop_window > 0) a request also
+finishes as soon as every one of its fits has stopped: each tick enqueues a
+copy of the pool's per-slot stopped flags to pinned memory and a later tick
+reads it.
 
 All arithmetic runs in the library's kernels; this module is bookkeeping:
 slot allocation, queues, tick pacing and latency timestamps.
@@ -76,6 +80,7 @@ class Request:
     steps: int = 0
     t_admit: float = 0.0
     t_done: float = 0.0
+    admit_tick: int = -1
     params: torch.Tensor | None = None   # pinned host results
     status: torch.Tensor | None = None
     chi2: torch.Tensor | None = None
@@ -98,6 +103,14 @@ class Lane:
         self.active: list[Request] = []
         self.finishing: list[Request] = []
         self.tick_event: torch.cuda.Event | None = None
+        # stopped flags of the slots (stopping rules): device copy, pinned
+        # host copy, the event that marks the host copy complete and the
+        # tick at which the flags were taken
+        self.done_dev = self.done_host = self.snap_event = None
+        self.snap_tick = -1
+        if pool.stop_window > 0:
+            self.done_dev = torch.zeros(pool.capacity, dtype=torch.int32, device=pool.device)
+            self.done_host = torch.zeros(pool.capacity, dtype=torch.int32, pin_memory=True)
 
     @property
     def footprint_bytes(self) -> int:
@@ -128,6 +141,7 @@ class Server:
             lane.queue.popleft()
             req.slot0 = slot0
             req.t_admit = now
+            req.admit_tick = self.ticks
             with torch.cuda.stream(lane.pool.stream):
                 lane.pool.load(slot0, req.obs, req.ivar, req.init, self.n_steps)
             lane.active.append(req)
@@ -168,9 +182,25 @@ class Server:
                 lane.pool.step(lane.alloc.high_water(), k)
                 for r in lane.active:
                     r.steps += k
-                for r in [r for r in lane.active if r.steps >= self.n_steps]:
+                fin = [r for r in lane.active if r.steps >= self.n_steps]
+                if lane.snap_event is not None and lane.snap_event.query():
+                    flags = lane.done_host.numpy()
+                    for r in lane.active:
+                        # flags taken before r was loaded belong to older fits
+                        if (r not in fin and r.admit_tick <= lane.snap_tick
+                                and flags[r.slot0:r.slot0 + r.n].all()):
+                            fin.append(r)
+                    lane.snap_event = None
+                for r in fin:
                     lane.active.remove(r)
                     self._finish(lane, r)
+                if lane.done_dev is not None and lane.snap_event is None and lane.active:
+                    hw = lane.alloc.high_water()
+                    lane.pool.progress(0, done=lane.done_dev[:hw])
+                    lane.done_host[:hw].copy_(lane.done_dev[:hw], non_blocking=True)
+                    lane.snap_event = torch.cuda.Event()
+                    lane.snap_event.record(lane.pool.stream)
+                    lane.snap_tick = self.ticks
                 lane.tick_event = torch.cuda.Event()
                 lane.tick_event.record(lane.pool.stream)
             if prev is not None:
