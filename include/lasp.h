@@ -59,6 +59,7 @@ extern "C" {
 #define LASP_ST_STOP_FLAT 0x40u       /* stopped: loss changed < stop_tol over the window */
 #define LASP_ST_STOP_RISING 0x80u     /* stopped: loss rose at every step of the window */
 #define LASP_ST_NOT_CONVERGED 0x100u  /* stopping rules on, step limit reached first */
+#define LASP_ST_POLISH_LIMIT 0x200u   /* polish reached polish_iters before its stopping test */
 
 #define LASP_PREC_FP32 0   /* FP32 interpolator contraction */
 #define LASP_PREC_BF16X3 1 /* BF16 hi/lo split contraction, FP32 accumulate */
@@ -100,6 +101,17 @@ extern "C" {
  *                  paper's window is 50 and its threshold 1e-5.  A stopped
  *                  fit takes no further steps; the others are not affected.
  *  out_steps       optional device int32 [n_spec]: Adam steps each fit took.
+ *  polish_iters    after the Adam steps, up to this many Levenberg-Marquardt
+ *                  iterations per spectrum (0 = none): damped Gauss-Newton
+ *                  steps on the residual with the continuum profiled out,
+ *                  (S + lambda diag S) du = Ju^T W e, kept when chi2 falls;
+ *                  a spectrum stops when the predicted chi2 decrease of its
+ *                  next step du^T q is below 1e-6, when an accepted step
+ *                  lowers chi2 by less than 1e-10 relative or moves u by
+ *                  less than 1e-7, or when lambda exceeds 1e10
+ *                  (LASP_ST_POLISH_LIMIT if the iteration limit came first).  The paper proposes adding curvature
+ *                  information to its Adam stage (Section 5); n_steps = 0
+ *                  with polish_iters > 0 is a plain LM fit.
  */
 typedef struct lasp_opts {
   int32_t n_spec;
@@ -121,13 +133,14 @@ typedef struct lasp_opts {
   int32_t stop_window;
   float stop_tol;
   int32_t *out_steps;
+  int32_t polish_iters;
 } lasp_opts;
 
 /* Defaults: n_basis 20, margin 64, degree 10, FP32, box
  * lo = (log10 4000, 1, -2.5, -300, 50), hi = (log10 8000, 5, 0.5, 300, 150),
  * lr 1e-2, betas (0.9, 0.999), eps 1e-8, weight_quantile 0.5, no arms,
  * null stream, no status/chi2 outputs, stopping rules off (stop_window 0,
- * stop_tol 1e-5), no out_steps.  n_spec and n_pix are set to 0. */
+ * stop_tol 1e-5), no out_steps, no polish.  n_spec and n_pix are set to 0. */
 void lasp_default_opts(lasp_opts *opts);
 
 /*

@@ -16,6 +16,7 @@ from .lasp import (  # noqa: F401
     ST_NONFINITE_INPUT,
     ST_NOT_CONVERGED,
     ST_OUT_OF_BOX,
+    ST_POLISH_LIMIT,
     ST_SIGMA_FLOOR,
     ST_SINGULAR,
     ST_STOP_FLAT,

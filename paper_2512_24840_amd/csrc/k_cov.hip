@@ -10,7 +10,10 @@
 // forward mode: dF''/du_t = G (x) dF'/du_t for t = 1..3 (dF'/du_t from the
 // derivative rows of the interpolator contraction) and
 // dF''/du_{4,5} = (dG/dmu, dG/dsigma) (x) F' times the chain factors.
-// Optionally the model Jacobian d(C F'')/du at fixed continuum is written.
+// Optionally the model Jacobian d(C F'')/du at fixed continuum is written,
+// and the Gauss-Newton normal equations of the profiled residual, S du = q
+// with q = Ju^T W e (no continuum term: Jb^T W e = 0 at the least-squares
+// continuum), for the Levenberg-Marquardt polish.
 #include "lasp_internal.h"
 
 namespace lasp {
@@ -21,20 +24,25 @@ constexpr int kOffF = 16;
 struct CovLayout {
   int ks;
   int k_off;   // floats: taps [n_arms][3][ks]
-  int d_off;   // bytes: doubles
+  int d_off;   // floats: columns dF''/du_{1..3} [3][kNPL * block], lane-major pixels
+  int x_off;   // bytes: doubles
   int bytes;
 };
 
+// The staged F' row region (floats [0, k_off)) is reused as the reduction
+// scratch of block_sum_lds once every convolution is done.
 __host__ __device__ inline CovLayout cov_layout(const Geometry &g, int nwaves) {
   CovLayout L;
+  int cols = kOffF + (g.ldF > kNPL * g.block ? g.ldF : kNPL * g.block) + 32;
+  if (cols < nwaves * 1024) cols = nwaves * 1024;
   L.ks = ((2 * g.M + 1 + 7) & ~7) + 8;
-  const int sf_len = kOffF + g.ldF + 32;
-  L.k_off = (sf_len + 3) & ~3;
-  const int fl_end = L.k_off + g.n_arms * 3 * L.ks;
-  L.d_off = ((fl_end * 4) + 15) & ~15;
-  // doubles: reduction [nwaves][64], moments [64], JuJu [32], X [16][8],
-  // work [64], scalars [16]
-  L.bytes = L.d_off + 8 * (nwaves * 64 + 64 + 32 + 128 + 64 + 16);
+  L.k_off = (cols + 3) & ~3;
+  L.d_off = (L.k_off + g.n_arms * 3 * L.ks + 3) & ~3;
+  const int fl_end = L.d_off + 3 * kNPL * g.block;
+  L.x_off = ((fl_end * 4) + 15) & ~15;
+  // doubles: reduction [nwaves][64], moments [64], JuJu + q + chi2 [32],
+  // X [16][8], work [64], scalars [16]
+  L.bytes = L.x_off + 8 * (nwaves * 64 + 64 + 32 + 128 + 64 + 16);
   return L;
 }
 
@@ -42,18 +50,21 @@ template <int BLOCK, int ND>
 __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0, double bhi0,
                                                double blo1, double bhi1, double blo2, double bhi2,
                                                double out_scale3, double out_scale4,
-                                               double *out_cov, float *out_jac) {
+                                               double *out_cov, float *out_jac,
+                                               double *out_normal, const int *active) {
   constexpr int NW = BLOCK / 64;
   constexpr int NNU = 2 * ND - 1;
   constexpr int NMOM = NNU + ND;
   constexpr int NWIN = kNPL + kTB - 1;
+  constexpr int NCOL = kNPL * BLOCK;  // stride of one staged column
   extern __shared__ __align__(16) unsigned char smem[];
   const CovLayout L = cov_layout(g, NW);
   float *sF = reinterpret_cast<float *>(smem);
   float *sK = sF + L.k_off;
-  double *sRed = reinterpret_cast<double *>(smem + L.d_off);
+  float *sD = sF + L.d_off;
+  double *sRed = reinterpret_cast<double *>(smem + L.x_off);
   double *sMom = sRed + NW * 64;
-  double *sJJ = sMom + 64;
+  double *sJJ = sMom + 64;    // JuJu packed [15], q [5], chi2
   double *sX = sJJ + 32;      // [ND][5]
   double *sW = sX + 128;      // work
   double *sScal = sW + 64;
@@ -62,11 +73,14 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
   float *sCs = reinterpret_cast<float *>(sScal + 12);   // [kMaxArms] chain factor for sigma
 
   const int spec = blockIdx.x;
+  if (active && !active[spec]) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int P = g.P, M = g.M;
   const int j0 = tid * kNPL;
   const bool has_pix = j0 < P;
   const bool multi = g.n_arms > 1;
+
+  for (int q = tid; q < 3 * NCOL; q += BLOCK) sD[q] = 0.f;
 
   // ---- taps G, dG/dmu, dG/dsigma per arm ---------------------------------
   const double u4 = (double)s.u[(size_t)spec * kNP + 3];
@@ -90,7 +104,7 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
       for (int k = 0; k < 3; ++k) {
         const int idx = lane + 64 * k;
         double v = 0.0, d = 0.0;
-        if (idx < T) {
+        if (64 * k < T && idx < T) {
           d = (double)(idx - H) - mu;
           v = exp(-d * d / (2.0 * spx * spx));
         }
@@ -127,14 +141,12 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
     }
   }
 
-  // ---- forward-mode columns: F'' and dF''/du_t, one staged row at a time --
-  float f[kNPL], d[kNP][kNPL];
+  // ---- forward-mode columns: F'' and dF''/du_t, one staged row at a time.
+  //      Row 0 gives F'' and the mu, sigma columns (kept in registers); rows
+  //      1..3 give the u1..u3 columns (kept in LDS) -----------------------
+  float f[kNPL], d3[kNPL], d4[kNPL];
 #pragma unroll
-  for (int i = 0; i < kNPL; ++i) {
-    f[i] = 0.f;
-#pragma unroll
-    for (int t = 0; t < kNP; ++t) d[t][i] = 0.f;
-  }
+  for (int i = 0; i < kNPL; ++i) f[i] = d3[i] = d4[i] = 0.f;
   const int wp0 = wave * 64 * kNPL;
   const int wp1 = min(wp0 + 64 * kNPL, P) - 1;
   int wa_lo = 0, wa_hi = 0;
@@ -142,13 +154,19 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
     if (g.arm_start[a] <= wp0) wa_lo = a;
     if (g.arm_start[a] <= wp1) wa_hi = a;
   }
+  constexpr int kStage = (kNPL * BLOCK / 4 + BLOCK - 1) / BLOCK;
+  const int n4 = g.ldF / 4;
   for (int row = 0; row < 4; ++row) {
     __syncthreads();
     {
-      const float4 *src =
-          reinterpret_cast<const float4 *>(s.fp + (size_t)spec * s.fp_stride + (size_t)row * g.ldF);
-      for (int q = tid; q < g.ldF / 4; q += BLOCK)
-        *reinterpret_cast<float4 *>(sF + kOffF + 4 * q) = src[q];
+      const float4 *src = reinterpret_cast<const float4 *>(s.fp + (size_t)spec * s.fp_stride +
+                                                           (size_t)row * g.ldF);
+      float4 fst[kStage];
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) fst[k] = src[min(tid + k * BLOCK, n4 - 1)];
+#pragma unroll
+      for (int k = 0; k < kStage; ++k)
+        *reinterpret_cast<float4 *>(sF + kOffF + 4 * min(tid + k * BLOCK, n4 - 1)) = fst[k];
       for (int q = tid; q < kOffF; q += BLOCK) sF[q] = 0.f;
       for (int q = tid; q < 32; q += BLOCK) sF[kOffF + g.ldF + q] = 0.f;
     }
@@ -156,7 +174,7 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
     if (!has_pix) continue;
     for (int a = wa_lo; a <= wa_hi; ++a) {
       const int H = sHa[a], T = 2 * H + 1;
-      const int nk = row == 0 ? 3 : 1;  // row 0 also gives the mu and sigma columns
+      const int nk = row == 0 ? 3 : 1;
       float acc[3][kNPL];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
@@ -188,26 +206,26 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
         if (j0 + i >= lo && j0 + i < hi) {
           if (row == 0) {
             f[i] = acc[0][i];
-            d[3][i] = cmu * acc[1][i];
-            d[4][i] = cs * acc[2][i];
+            d3[i] = cmu * acc[1][i];
+            d4[i] = cs * acc[2][i];
           } else {
-#pragma unroll
-            for (int t = 0; t < 3; ++t)
-              if (row == t + 1) d[t][i] = acc[0][i];
+            sD[(row - 1) * NCOL + j0 + i] = acc[0][i];
           }
         }
       }
     }
   }
-
+  // data (lane-major, coalesced)
   float2 ow[kNPL];
   {
     const float2 *src = s.ow + (size_t)spec * kNPL * BLOCK + tid;
 #pragma unroll
     for (int i = 0; i < kNPL; ++i) ow[i] = src[i * BLOCK];
   }
+  __syncthreads();  // every read of the staged row is done: sF becomes scratch
+  double *scratch = reinterpret_cast<double *>(sF);
 
-  // ---- continuum least squares at the final point (as in the fused pass) --
+  // ---- continuum least squares (as in the fused pass) ---------------------
   {
     double acc[NMOM];
 #pragma unroll
@@ -232,8 +250,9 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
         tm = tc;
         tc = tn;
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    block_sum_doubles<NW, NMOM>(acc, sRed, sMom, lane, wave);
+    block_sum_lds<NW, NMOM>(acc, scratch, sRed, sMom, lane, wave);
   }
   if (wave == 0) {
     double a[ND + 1];
@@ -249,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
     for (int k = 0; k < ND; ++k) {
       double piv[ND + 1];
 #pragma unroll
-      for (int n = k; n <= ND; ++n) piv[n] = __shfl(a[n], k, 64);
+      for (int n = k; n <= ND; ++n) piv[n] = read_lane(a[n], k);
       ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
       const double rp = 1.0 / piv[k];
       if (lane == k) {
@@ -267,14 +286,23 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
   }
   __syncthreads();
 
-  // ---- residual Jacobian columns ju_t = C dF''/du_t; chi2 ------------------
-  float C[kNPL];
-  double chi2_part = 0.0;
+  // ---- one pass per pixel: continuum C, residual e, the residual Jacobian
+  //      columns ju_t = C dF''/du_t (scaled in place: registers for mu and
+  //      sigma, LDS for u1..u3), and Ju^T W Ju (15), q = Ju^T W e (5) and
+  //      chi2 in FP64 ------------------------------------------------------
   {
     float c[ND];
 #pragma unroll
     for (int k = 0; k < ND; ++k) c[k] = sBf[k];
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      opaque(f[i]);
+      opaque(ow[i]);
+    }
     const float two_over_p = 2.f / (float)P;
+    double acc[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) acc[k] = 0.0;
 #pragma unroll
     for (int i = 0; i < kNPL; ++i) {
       const float x = fmaf((float)(j0 + i), two_over_p, -1.f);
@@ -285,56 +313,69 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
         b2 = b1;
         b1 = bk;
       }
-      C[i] = fmaf(x, b1, c[0] - b2);
-      const float e = ow[i].x - C[i] * f[i];
-      chi2_part = fma((double)(ow[i].y * e), (double)e, chi2_part);
+      const float C = fmaf(x, b1, c[0] - b2);
+      const float e = ow[i].x - C * f[i];
+      double dd[kNP];
 #pragma unroll
-      for (int t = 0; t < kNP; ++t) d[t][i] *= C[i];
-    }
-  }
-  if (out_jac) {
-    const float wsc = s.wscale[spec];
-#pragma unroll
-    for (int i = 0; i < kNPL; ++i)
-      if (j0 + i < P)
-#pragma unroll
-        for (int t = 0; t < kNP; ++t)
-          out_jac[((size_t)spec * kNP + t) * P + j0 + i] = d[t][i] * wsc;
-  }
-  if (out_cov == nullptr) return;
-
-  // Ju^T Ju (15 entries, FP64) and chi2
-  {
-    double acc[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-#pragma unroll
-    for (int i = 0; i < kNPL; ++i) {
+      for (int t = 0; t < 3; ++t) {
+        // j0 + i < kNPL * BLOCK for every thread; columns are zero where no
+        // pixel is
+        const float v = sD[t * NCOL + j0 + i] * C;
+        sD[t * NCOL + j0 + i] = v;
+        dd[t] = (double)v;
+      }
+      d3[i] *= C;
+      d4[i] *= C;
+      dd[3] = (double)d3[i];
+      dd[4] = (double)d4[i];
       const double w = (double)ow[i].y;
+      const double we = w * (double)e;
       int k = 0;
 #pragma unroll
-      for (int p = 0; p < kNP; ++p)
+      for (int p = 0; p < kNP; ++p) {
+        const double wd = w * dd[p];
 #pragma unroll
-        for (int q = 0; q <= p; ++q) acc[k++] += w * (double)d[p][i] * (double)d[q][i];
+        for (int q = 0; q <= p; ++q) acc[k++] += wd * dd[q];
+      }
+#pragma unroll
+      for (int p = 0; p < kNP; ++p) acc[15 + p] = fma(we, dd[p], acc[15 + p]);
+      acc[20] = fma(we, (double)e, acc[20]);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    acc[15] = chi2_part;
-    block_sum_doubles<NW, 16>(acc, sRed, sJJ, lane, wave);
+    if (out_jac && has_pix) {
+      const float wsc = s.wscale[spec];
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i)
+        if (j0 + i < P) {
+          float *o = out_jac + (size_t)spec * kNP * P + j0 + i;
+#pragma unroll
+          for (int t = 0; t < 3; ++t) o[(size_t)t * P] = sD[t * NCOL + j0 + i] * wsc;
+          o[(size_t)3 * P] = d3[i] * wsc;
+          o[(size_t)4 * P] = d4[i] * wsc;
+        }
+    }
+    if (out_cov == nullptr && out_normal == nullptr) return;
+    block_sum_lds<NW, 21>(acc, scratch, sRed, sJJ, lane, wave);
   }
-  // X[n][t] = Jb^T Ju = sum W F'' T_n ju_t (Chebyshev T_n)
-#pragma unroll 1
-  for (int t = 0; t < kNP; ++t) {
+  // X[n][t] = Jb^T W Ju = sum W F'' T_n ju_t (Chebyshev T_n).  One pass per
+  // column; the register columns get passes of their own (selecting between
+  // them in one pass would make the compiler keep them in memory).
+  auto xpass = [&](int t, auto column) {
+    int jb = j0;
+    opaque(jb);
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      opaque(f[i]);
+      opaque(ow[i]);
+    }
     double acc[ND];
 #pragma unroll
     for (int n = 0; n < ND; ++n) acc[n] = 0.0;
     const double two_over_p = 2.0 / (double)P;
 #pragma unroll
     for (int i = 0; i < kNPL; ++i) {
-      float dti = d[0][i];
-#pragma unroll
-      for (int q = 1; q < kNP; ++q)
-        if (q == t) dti = d[q][i];
-      const double x = fma((double)(j0 + i), two_over_p, -1.0);
-      const double v = (double)ow[i].y * (double)f[i] * (double)dti;
+      const double x = fma((double)(jb + i), two_over_p, -1.0);
+      const double v = (double)ow[i].y * (double)f[i] * (double)column(i);
       double tm = 1.0, tc = x;
       acc[0] += v;
       acc[1] = fma(v, x, acc[1]);
@@ -346,10 +387,14 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
         tc = tn;
       }
     }
-    block_sum_doubles<NW, ND>(acc, sRed, sW, lane, wave);
+    block_sum_lds<NW, ND>(acc, scratch, sRed, sW, lane, wave);
     if (tid < ND) sX[tid * kNP + t] = sW[tid];
     __syncthreads();
-  }
+  };
+#pragma unroll 1
+  for (int t = 0; t < 3; ++t) xpass(t, [&](int i) { return sD[t * NCOL + j0 + i]; });
+  xpass(3, [&](int i) { return d3[i]; });
+  xpass(4, [&](int i) { return d4[i]; });
 
   // ---- wave 0: Y = A^{-1} X, S = JuJu - X^T Y, Sigma_u = s^2 S^{-1} --------
   if (wave == 0) {
@@ -368,7 +413,7 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
     for (int k = 0; k < ND; ++k) {
       double piv[NC];
 #pragma unroll
-      for (int n = k; n < NC; ++n) piv[n] = __shfl(a[n], k, 64);
+      for (int n = k; n < NC; ++n) piv[n] = read_lane(a[n], k);
       ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
       const double rp = 1.0 / piv[k];
       if (lane == k) {
@@ -402,70 +447,85 @@ __global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0,
       sr[q] = v;
       sr[kNP + q] = (r == q) ? 1.0 : 0.0;
     }
+    if (out_normal && lane < kNP) {
+      // Gauss-Newton normal equations of the residual with the continuum
+      // profiled out: S du = q (rows of S, then q, then chi2)
+      double *o = out_normal + (size_t)spec * kNormalStride;
 #pragma unroll
-    for (int k = 0; k < kNP; ++k) {
-      double piv[2 * kNP];
-#pragma unroll
-      for (int n = 0; n < 2 * kNP; ++n) piv[n] = __shfl(sr[n], k, 64);
-      ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
-      const double rp = 1.0 / piv[k];
-      if (lane == k) {
-#pragma unroll
-        for (int n = 0; n < 2 * kNP; ++n) sr[n] *= rp;
-      } else {
-        const double fct = sr[k] * rp;
-#pragma unroll
-        for (int n = 0; n < 2 * kNP; ++n) sr[n] = fma(-fct, piv[n], sr[n]);
-      }
+      for (int q = 0; q < kNP; ++q) o[lane * kNP + q] = sr[q];
+      o[25 + lane] = sJJ[15 + lane];
+      if (lane == 0) o[30] = ok ? sJJ[20] : NAN;
     }
-    const int n_eff = s.neff[spec];
-    const double chi2 = sJJ[15];
-    const double s2 = n_eff > kNP ? chi2 / (double)(n_eff - kNP) : NAN;
-    if (lane < kNP) {
-      // physical units: Teff via dTeff = Teff ln10 dlog10Teff, the others by
-      // the box half-widths
-      const double lt = blo0 + 0.5 * ((double)s.u[(size_t)spec * kNP] + 1.0) * (bhi0 - blo0);
-      double jd[kNP];
-      jd[0] = 0.5 * (bhi0 - blo0) * exp10(lt) * kLn10;
-      jd[1] = 0.5 * (bhi1 - blo1);
-      jd[2] = 0.5 * (bhi2 - blo2);
-      jd[3] = out_scale3;
-      jd[4] = out_scale4;
-      double jr = jd[0];
+    if (out_cov) {
 #pragma unroll
-      for (int q = 1; q < kNP; ++q)
-        if (q == lane) jr = jd[q];
+      for (int k = 0; k < kNP; ++k) {
+        double piv[2 * kNP];
 #pragma unroll
-      for (int q = 0; q < kNP; ++q) {
-        const double v = ok ? s2 * sr[kNP + q] * jr * jd[q] : NAN;
-        out_cov[((size_t)spec * kNP + lane) * kNP + q] = v;
+        for (int n = 0; n < 2 * kNP; ++n) piv[n] = read_lane(sr[n], k);
+        ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
+        const double rp = 1.0 / piv[k];
+        if (lane == k) {
+#pragma unroll
+          for (int n = 0; n < 2 * kNP; ++n) sr[n] *= rp;
+        } else {
+          const double fct = sr[k] * rp;
+#pragma unroll
+          for (int n = 0; n < 2 * kNP; ++n) sr[n] = fma(-fct, piv[n], sr[n]);
+        }
       }
+      const int n_eff = s.neff[spec];
+      const double chi2 = sJJ[20];
+      const double s2 = n_eff > kNP ? chi2 / (double)(n_eff - kNP) : NAN;
+      if (lane < kNP) {
+        // physical units: Teff via dTeff = Teff ln10 dlog10Teff, the others by
+        // the box half-widths
+        const double lt = blo0 + 0.5 * ((double)s.u[(size_t)spec * kNP] + 1.0) * (bhi0 - blo0);
+        double jd[kNP];
+        jd[0] = 0.5 * (bhi0 - blo0) * exp10(lt) * kLn10;
+        jd[1] = 0.5 * (bhi1 - blo1);
+        jd[2] = 0.5 * (bhi2 - blo2);
+        jd[3] = out_scale3;
+        jd[4] = out_scale4;
+        double jr = jd[0];
+#pragma unroll
+        for (int q = 1; q < kNP; ++q)
+          if (q == lane) jr = jd[q];
+#pragma unroll
+        for (int q = 0; q < kNP; ++q) {
+          const double v = ok ? s2 * sr[kNP + q] * jr * jd[q] : NAN;
+          out_cov[((size_t)spec * kNP + lane) * kNP + q] = v;
+        }
+      }
+      if (lane == 0 && !ok) s.status[spec] |= kStSingular;
     }
-    if (lane == 0 && !ok) s.status[spec] |= kStSingular;
   }
 }
 
 template <int BLOCK, int ND>
 hipError_t launch_cov_t(const Geometry &g, const State &s, const double *lo, const double *hi,
-                        double *out_cov, float *out_jac, hipStream_t st) {
+                        double *out_cov, float *out_jac, double *out_normal, const int *active,
+                        hipStream_t st) {
   const CovLayout L = cov_layout(g, BLOCK / 64);
   auto k = k_cov<BLOCK, ND>;
   hipError_t e =
       hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, lo[0], hi[0], lo[1], hi[1],
-                     lo[2], hi[2], 0.5 * (hi[3] - lo[3]), 0.5 * (hi[4] - lo[4]), out_cov, out_jac);
+                     lo[2], hi[2], 0.5 * (hi[3] - lo[3]), 0.5 * (hi[4] - lo[4]), out_cov, out_jac,
+                     out_normal, active);
   return hipGetLastError();
 }
 
 template <int BLOCK>
 hipError_t launch_cov_b(const Geometry &g, const State &s, const double *lo, const double *hi,
-                        double *out_cov, float *out_jac, hipStream_t st) {
+                        double *out_cov, float *out_jac, double *out_normal, const int *active,
+                        hipStream_t st) {
   switch (g.nd) {
-    case 5: return launch_cov_t<BLOCK, 5>(g, s, lo, hi, out_cov, out_jac, st);
-    case 7: return launch_cov_t<BLOCK, 7>(g, s, lo, hi, out_cov, out_jac, st);
-    case 9: return launch_cov_t<BLOCK, 9>(g, s, lo, hi, out_cov, out_jac, st);
-    case 11: return launch_cov_t<BLOCK, 11>(g, s, lo, hi, out_cov, out_jac, st);
+    case 5: return launch_cov_t<BLOCK, 5>(g, s, lo, hi, out_cov, out_jac, out_normal, active, st);
+    case 7: return launch_cov_t<BLOCK, 7>(g, s, lo, hi, out_cov, out_jac, out_normal, active, st);
+    case 9: return launch_cov_t<BLOCK, 9>(g, s, lo, hi, out_cov, out_jac, out_normal, active, st);
+    case 11:
+      return launch_cov_t<BLOCK, 11>(g, s, lo, hi, out_cov, out_jac, out_normal, active, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -473,11 +533,12 @@ hipError_t launch_cov_b(const Geometry &g, const State &s, const double *lo, con
 }  // namespace
 
 hipError_t launch_cov(const Geometry &g, const State &s, const double *lo, const double *hi,
-                      double *out_cov, float *out_jac, hipStream_t st) {
+                      double *out_cov, float *out_jac, double *out_normal, const int *active,
+                      hipStream_t st) {
   switch (g.block) {
-    case 128: return launch_cov_b<128>(g, s, lo, hi, out_cov, out_jac, st);
-    case 256: return launch_cov_b<256>(g, s, lo, hi, out_cov, out_jac, st);
-    case 512: return launch_cov_b<512>(g, s, lo, hi, out_cov, out_jac, st);
+    case 128: return launch_cov_b<128>(g, s, lo, hi, out_cov, out_jac, out_normal, active, st);
+    case 256: return launch_cov_b<256>(g, s, lo, hi, out_cov, out_jac, out_normal, active, st);
+    case 512: return launch_cov_b<512>(g, s, lo, hi, out_cov, out_jac, out_normal, active, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -34,8 +34,9 @@ int dev_fail(hipError_t e, const char *where) {
 struct Workspace {
   int device = 0;
   hipStream_t stream = nullptr;
-  size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0, cap_hist = 0;
+  size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0, cap_hist = 0, cap_lm = 0;
   State s{};
+  lasp::LmState lm{};
 };
 
 std::mutex g_mu;
@@ -62,24 +63,32 @@ void free_ws(Workspace *w) {
                   s.chi2,     s.basis,    s.basis_hi, s.basis_lo, s.basis_thi, s.basis_tlo};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  lasp::LmState &l = w->lm;
+  void *lptrs[] = {l.normal, l.lambda, l.chi2_trial, l.step_inf, l.u_trial, l.st_trial,
+                   l.need_jac, l.flags};
+  for (void *p : lptrs)
+    if (p) (void)hipFree(p);
   w->s = State{};
-  w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = w->cap_hist = 0;
+  w->lm = lasp::LmState{};
+  w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = w->cap_hist = w->cap_lm = 0;
 }
 
 // Grows the buffers of w to hold g.B spectra of geometry g (fp_rows rows of F'
 // per spectrum, a loss history of hist_w entries when the stopping rules are
 // on).  Earlier work on the stream may still use old buffers, so the stream
 // is synchronised before anything is freed.
-int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hipStream_t st) {
+int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hipStream_t st,
+                   bool lm = false) {
   const size_t B = (size_t)g.B;
   const size_t need_hist = B * (size_t)hist_w;
+  const size_t need_lm = lm ? B : 0;
   const size_t need_ow = B * lasp::kNPL * g.block;
   const size_t need_fp = B * fp_rows * g.ldF;
   const size_t need_fbar = B * g.ldF;
   const size_t need_basis = (size_t)lasp::kNB * g.ldF;
   const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
                       need_fbar > w->cap_fbar || need_basis > w->cap_basis ||
-                      need_hist > w->cap_hist || !w->s.u;
+                      need_hist > w->cap_hist || need_lm > w->cap_lm || !w->s.u;
   if (!regrow) return LASP_OK;
   hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
@@ -103,6 +112,20 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
     if (r == hipSuccess) w->cap_B = B;
   }
   if (r == hipSuccess && need_hist > 0) r = grow(s.lhist, w->cap_hist, need_hist);
+  if (r == hipSuccess && need_lm > w->cap_lm) {
+    lasp::LmState &l = w->lm;
+    const size_t cl = w->cap_lm;
+    size_t a1 = cl, a2 = cl, a3 = cl, a4 = cl, a5 = cl, a6 = cl, a7 = cl, a8 = cl;
+    r = grow(l.normal, a1, need_lm * lasp::kNormalStride);
+    if (r == hipSuccess) r = grow(l.lambda, a2, need_lm);
+    if (r == hipSuccess) r = grow(l.chi2_trial, a3, need_lm);
+    if (r == hipSuccess) r = grow(l.step_inf, a4, need_lm);
+    if (r == hipSuccess) r = grow(l.u_trial, a5, need_lm * lasp::kNP);
+    if (r == hipSuccess) r = grow(l.st_trial, a6, need_lm);
+    if (r == hipSuccess) r = grow(l.need_jac, a7, need_lm);
+    if (r == hipSuccess) r = grow(l.flags, a8, need_lm);
+    if (r == hipSuccess) w->cap_lm = need_lm;
+  }
   if (r == hipSuccess) r = grow(s.ow, w->cap_ow, need_ow);
   if (r == hipSuccess) r = grow(s.fp, w->cap_fp, need_fp);
   if (r == hipSuccess) r = grow(s.fbar, w->cap_fbar, need_fbar);
@@ -126,7 +149,8 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
   return LASP_OK;
 }
 
-int get_workspace(const Geometry &g, int fp_rows, int hist_w, hipStream_t st, Workspace **out) {
+int get_workspace(const Geometry &g, int fp_rows, int hist_w, hipStream_t st, Workspace **out,
+                  bool lm = false) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
@@ -139,7 +163,7 @@ int get_workspace(const Geometry &g, int fp_rows, int hist_w, hipStream_t st, Wo
     w->stream = st;
     g_ws[key] = w;
   }
-  int rc = ensure_buffers(w, g, fp_rows, hist_w, st);
+  int rc = ensure_buffers(w, g, fp_rows, hist_w, st, lm);
   if (rc) return rc;
   *out = w;
   return LASP_OK;
@@ -189,6 +213,8 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
     return fail(LASP_E_ARG, "stop_window must be in [0, 4096]");
   if (!(o->stop_tol >= 0.f) || !std::isfinite(o->stop_tol))
     return fail(LASP_E_ARG, "stop_tol must be finite and >= 0");
+  if (o->polish_iters < 0 || o->polish_iters > 1000)
+    return fail(LASP_E_ARG, "polish_iters must be in [0, 1000]");
   if (!wave_grid) return fail(LASP_E_ARG, "wave_grid is NULL");
 
   const int P = o->n_pix;
@@ -408,7 +434,8 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   hipStream_t st = (hipStream_t)opts->stream;
   Workspace *w = nullptr;
   const int W = opts->stop_window;
-  rc = get_workspace(g, out_cov ? 4 : 1, W, st, &w);
+  const int polish = opts->polish_iters;
+  rc = get_workspace(g, (out_cov || polish) ? 4 : 1, W, st, &w, polish > 0);
   if (rc) return rc;
   State s = w->s;
   if (W == 0) s.target = nullptr;  // every spectrum takes n_steps steps
@@ -440,12 +467,36 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   // chi2 and status at the returned parameters (every spectrum, stopped or
   // not); derivative rows for the covariance
   s.target = nullptr;
+  if (polish > 0) {
+    // Levenberg-Marquardt polish from the Adam end point
+    const lasp::LmState lm = w->lm;
+    State trial = s;
+    trial.u = lm.u_trial;
+    trial.chi2 = lm.chi2_trial;
+    trial.status = lm.st_trial;
+    trial.fp_stride = g.ldF;
+    LASP_CHECK(lasp::launch_lm_init(g, lm, st), "polish init");
+    for (int it = 0; it < polish; ++it) {
+      s.fp_stride = 4 * g.ldF;
+      LASP_CHECK(lasp::launch_interp_fwd(g, s, 1, bf16, st), "interpolator contraction");
+      {
+        LASP_TIMED(LASP_K_COV, st);
+        LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, nullptr, nullptr, lm.normal,
+                                    lm.need_jac, st),
+                   "normal equations");
+      }
+      LASP_CHECK(lasp::launch_lm_solve(g, s, lm, st), "polish step");
+      LASP_CHECK(lasp::launch_interp_fwd(g, trial, 0, bf16, st), "interpolator contraction");
+      LASP_CHECK(lasp::launch_fused(g, trial, 0, nullptr, st), "fused pass");
+      LASP_CHECK(lasp::launch_lm_accept(g, s, lm, it == polish - 1, st), "polish accept");
+    }
+  }
   s.fp_stride = out_cov ? 4 * g.ldF : g.ldF;
   LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, bf16, st), "interpolator contraction");
   LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, st), "fused pass");
   if (out_cov) {
     LASP_TIMED(LASP_K_COV, st);
-    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, nullptr, st),
+    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, nullptr, nullptr, nullptr, st),
                "covariance");
   }
   {
@@ -501,7 +552,7 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid, c
   }
   if (rows4) {
     LASP_TIMED(LASP_K_COV, st);
-    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, out_jac, st),
+    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, out_jac, nullptr, nullptr, st),
                "covariance / model Jacobian");
   }
   LASP_CHECK(lasp::launch_outputs(g, s, out_chi2, out_J, out_neff, opts->status, st), "outputs");
@@ -649,7 +700,8 @@ int lasp_pool_finish(lasp_pool *p, int32_t slot0, int32_t count, float *out_para
   LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, p->st), "fused pass");
   if (out_cov) {
     LASP_TIMED(LASP_K_COV, p->st);
-    LASP_CHECK(lasp::launch_cov(g, s, p->opts.box_lo, p->opts.box_hi, out_cov, nullptr, p->st),
+    LASP_CHECK(lasp::launch_cov(g, s, p->opts.box_lo, p->opts.box_hi, out_cov, nullptr, nullptr, nullptr,
+                                p->st),
                "covariance");
   }
   LASP_TIMED(LASP_K_FINALIZE, p->st);

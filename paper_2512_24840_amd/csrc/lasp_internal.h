@@ -26,7 +26,20 @@ constexpr uint32_t kStSigmaFloor = 0x20u;
 constexpr uint32_t kStStopFlat = 0x40u;
 constexpr uint32_t kStStopRising = 0x80u;
 constexpr uint32_t kStNotConverged = 0x100u;
+constexpr uint32_t kStPolishLimit = 0x200u;
 constexpr int kMaxStopWindow = 4096;
+
+// Levenberg-Marquardt polish: a spectrum stops when the predicted chi2
+// decrease of its next step is below kLmDecreaseTol (chi2 units: the
+// remaining improvement is 1e-3 standard deviations in any direction), when
+// an accepted step lowers chi2 by less than kLmDropTol relative or moves u
+// by less than kLmStepTol, or when the damping passes kLmLambdaMax.
+constexpr double kLmDecreaseTol = 1e-6;
+constexpr double kLmDropTol = 1e-10;
+constexpr double kLmStepTol = 1e-7;
+constexpr double kLmLambdaMax = 1e10;
+constexpr int kLmDone = 1;
+constexpr int kNormalStride = 32;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -73,6 +86,18 @@ struct State {
   uint16_t *basis_tlo; // [ldF][32] bf16 low part
 };
 
+// Per-spectrum state of the Levenberg-Marquardt polish.
+struct LmState {
+  double *normal;      // [B][kNormalStride] S (25), q (5), chi2 at the current u
+  double *lambda;      // [B] damping
+  double *chi2_trial;  // [B] chi2 at the trial point
+  double *step_inf;    // [B] max |du| of the trial step (NaN: no step)
+  float *u_trial;      // [B][5]
+  uint32_t *st_trial;  // [B] status of the trial evaluation (discarded)
+  int *need_jac;       // [B] 1: normal equations needed at the current u
+  int *flags;          // [B] kLmDone
+};
+
 struct AdamCfg {
   float lr, beta1, beta2, eps;
   int stop_window;  // 0: fixed step count
@@ -102,10 +127,18 @@ hipError_t launch_finalize(const Geometry &g, const State &s, const double *box_
                            double *chi2_out, int32_t *steps_out, hipStream_t st);
 hipError_t launch_progress(const Geometry &g, const State &s, int32_t *steps, int32_t *done,
                            hipStream_t st);
+// Covariance, model Jacobian and/or Gauss-Newton normal equations
+// (out_normal [B][kNormalStride]: S row-major [25], q [5], chi2) for the
+// spectra with active[spec] != 0 (every spectrum when active is NULL).
 hipError_t launch_cov(const Geometry &g, const State &s, const double *box_lo, const double *box_hi,
-                      double *out_cov, float *out_jac, hipStream_t st);
+                      double *out_cov, float *out_jac, double *out_normal, const int *active,
+                      hipStream_t st);
 hipError_t launch_outputs(const Geometry &g, const State &s, double *chi2_out, float *J_out,
                           int32_t *neff_out, uint32_t *status_out, hipStream_t st);
+hipError_t launch_lm_init(const Geometry &g, const LmState &lm, hipStream_t st);
+hipError_t launch_lm_solve(const Geometry &g, const State &s, const LmState &lm, hipStream_t st);
+hipError_t launch_lm_accept(const Geometry &g, const State &s, const LmState &lm, int last,
+                            hipStream_t st);
 bool fused_supported(int block, int nd);
 size_t fused_smem_bytes(const Geometry &g);
 
@@ -176,6 +209,14 @@ __device__ inline T wave_sum(T x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
+}
+
+// Makes the compiler treat x as a new value: computations from x after this
+// point are not merged with the same computations before it (which would
+// keep their results live across phases and raise register pressure).
+template <typename T>
+__device__ inline void opaque(T &x) {
+  asm volatile("" : "+v"(x));
 }
 
 // Value of v in lane l (l wave uniform), through scalar registers.

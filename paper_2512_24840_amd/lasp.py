@@ -30,6 +30,7 @@ ST_SIGMA_FLOOR = 0x20
 ST_STOP_FLAT = 0x40
 ST_STOP_RISING = 0x80
 ST_NOT_CONVERGED = 0x100
+ST_POLISH_LIMIT = 0x200
 PREC = {"fp32": 0, "bf16x3": 1}
 N_BASIS = 20
 N_PAR = 5
@@ -70,6 +71,7 @@ class LaspOpts(ctypes.Structure):
         ("stop_window", ctypes.c_int32),
         ("stop_tol", ctypes.c_float),
         ("out_steps", ctypes.c_void_p),
+        ("polish_iters", ctypes.c_int32),
     ]
 
 
@@ -154,7 +156,7 @@ class Arms:
 
 def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
               betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5, arms: Arms | None = None,
-              box=None, stream=None, stop_window=0, stop_tol=1e-5) -> LaspOpts:
+              box=None, stream=None, stop_window=0, stop_tol=1e-5, polish_iters=0) -> LaspOpts:
     o = LaspOpts()
     load().lasp_default_opts(ctypes.byref(o))
     o.n_spec, o.n_pix, o.margin, o.degree = int(n_spec), int(n_pix), int(margin), int(degree)
@@ -162,6 +164,7 @@ def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
     o.lr, o.beta1, o.beta2, o.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
     o.weight_quantile = float(weight_quantile)
     o.stop_window, o.stop_tol = int(stop_window), float(stop_tol)
+    o.polish_iters = int(polish_iters)
     if box is not None:
         lo, hi = box
         for t in range(5):
@@ -195,9 +198,11 @@ class FitResult:
 def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=False,
               margin=64, degree=10, precision="fp32", lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
               weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
-              stop_window=0, stop_tol=1e-5, out: FitResult | None = None) -> FitResult:
+              stop_window=0, stop_tol=1e-5, polish_iters=0,
+              out: FitResult | None = None) -> FitResult:
     """lasp_fit_group on device tensors; returns after enqueueing (stream ordered).
-    stop_window > 0 turns on the per-spectrum stopping rules (window, stop_tol)."""
+    stop_window > 0 turns on the per-spectrum stopping rules (window, stop_tol);
+    polish_iters > 0 adds that many Levenberg-Marquardt iterations at most."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
@@ -215,7 +220,7 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
                         torch.empty(B, dtype=torch.int32, device=dev))
     o = make_opts(B, P, margin=margin, degree=degree, precision=precision, lr=lr, betas=betas,
                   eps=eps, weight_quantile=weight_quantile, arms=arms, box=box, stream=stream,
-                  stop_window=stop_window, stop_tol=stop_tol)
+                  stop_window=stop_window, stop_tol=stop_tol, polish_iters=polish_iters)
     o.status = ctypes.c_void_p(out.status.data_ptr())
     o.out_chi2 = ctypes.c_void_p(out.chi2.data_ptr())
     if out.steps is not None:
