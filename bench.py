@@ -54,6 +54,12 @@ def parse(argv=None):
     p.add_argument("--duration", type=float, default=20.0, help="serving: seconds of arrivals")
     p.add_argument("--rate", type=float, default=20000.0, help="serving: spectra/s offered")
     p.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32")
+    p.add_argument("--lm-iters", type=int, default=30,
+                   help="Levenberg-Marquardt iterations (at most) of the plain LM leg")
+    p.add_argument("--polish-adam-steps", type=int, default=100,
+                   help="Adam steps before the LM polish in the adam_lm leg")
+    p.add_argument("--polish-iters", type=int, default=15,
+                   help="LM iterations (at most) after the Adam steps in the adam_lm leg")
     p.add_argument("--serving-early-stop", action="store_true",
                    help="serving: requests finish when their fits meet the stopping rules")
     p.add_argument("--stop-window", type=int, default=50,
@@ -286,6 +292,24 @@ def main():
     status_es = res_es.status.cpu().numpy()
     params_es = res_es.params.cpu().numpy().astype(np.float64)
 
+    # Levenberg-Marquardt legs: a plain LM fit from the start point, and a
+    # short Adam run polished by LM (both with the covariance)
+    lm_legs = {}
+    for leg, (n_adam, n_lm) in (("lm", (0, args.lm_iters)),
+                                ("adam_lm", (args.polish_adam_steps, args.polish_iters))):
+        res_lm = lasp.fit_group(obs, ivar, grid, bas, init, n_adam, polish_iters=n_lm, **kw)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        lasp.fit_group(obs, ivar, grid, bas, init, n_adam, polish_iters=n_lm, out=res_lm, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_lm = e0.elapsed_time(e1) / 1e3
+        st_lm = res_lm.status.cpu().numpy()
+        lm_legs[leg] = dict(
+            t=t_lm, adam_steps=n_adam, lm_iters=n_lm,
+            params=res_lm.params.cpu().numpy().astype(np.float64),
+            limit=int(((st_lm & lasp.ST_POLISH_LIMIT) != 0).sum()))
+
     params = res.params.cpu().numpy().astype(np.float64)
     status = res.status.cpu().numpy()
     flops_spec, T = fused_flops_per_spectrum(params, shape)
@@ -337,6 +361,10 @@ def main():
             "not_converged": int(((status_es & lasp.ST_NOT_CONVERGED) != 0).sum()),
         },
     }
+    for leg, d in lm_legs.items():
+        out[leg] = {"value": B / d["t"], "unit": "spectra/s", "ms_per_group_fit": d["t"] * 1e3,
+                    "adam_steps": d["adam_steps"], "max_lm_iters": d["lm_iters"],
+                    "hit_iteration_limit": d["limit"]}
 
     if not args.no_cpu_baseline:
         import oracle
@@ -366,6 +394,12 @@ def main():
                                "max_abs_err": {k: float(v) for k, v in
                                                zip(("teff_K", "logg", "feh", "rv_kms"),
                                                    err.max(axis=0))}}
+        for leg, d in lm_legs.items():
+            e = np.abs(d["params"][:n] - refp)[:, :4]
+            out[leg]["oracle_match"] = {
+                "n": n, "matched": int(np.all(e <= FIT_TOL, axis=1).sum()),
+                "max_abs_err": {k: float(v) for k, v in zip(("teff_K", "logg", "feh", "rv_kms"),
+                                                            e.max(axis=0))}}
         err_es = np.abs(params_es[:n] - refp)[:, :4]
         out["early_stop"]["oracle_match"] = {
             "n": n, "matched": int(np.all(err_es <= FIT_TOL, axis=1).sum()),

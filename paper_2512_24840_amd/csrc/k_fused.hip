@@ -187,6 +187,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
         for (int q = 0; q < NWIN; ++q) w[q] = wsrc[q];
 #pragma unroll
         for (int t = 0; t < kTB; ++t) {
+          if (mb + t >= T) break;  // wave uniform: no work on the block's padding
           const float gk = K[mb + t];
 #pragma unroll
           for (int i = 0; i < kNPL; ++i) acc[i] = fmaf(gk, w[i - t + kTB - 1], acc[i]);
@@ -368,8 +369,10 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
 #pragma unroll
         for (int t = 0; t < kTB; ++t) {
           float acc = 0.f;
+          if (mb + t < T) {  // wave uniform
 #pragma unroll
-          for (int i = 0; i < kNPL; ++i) acc = fmaf(gm[i], w[i - t + kTB - 1], acc);
+            for (int i = 0; i < kNPL; ++i) acc = fmaf(gm[i], w[i - t + kTB - 1], acc);
+          }
           r[t] = acc;
         }
         // wave-wide sums of the kTB partials: transpose through LDS, each
@@ -384,9 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
           const float4 x0 = *reinterpret_cast<const float4 *>(sRt + tt * 64 + 8 * part);
           const float4 x1 = *reinterpret_cast<const float4 *>(sRt + tt * 64 + 8 * part + 4);
           float v = ((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w));
-          v += __shfl_xor(v, 1, 64);
-          v += __shfl_xor(v, 2, 64);
-          v += __shfl_xor(v, 4, 64);
+          v = group8_sum(v);
           if (part == 0) sRp[(wave * g.n_arms + a) * L.ks + mb + tt] = v;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -420,11 +421,17 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
         rgd += R * G * d;
         rgd2 += R * G * d * d;
       }
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      rg = wave_sum(rg);
-      rgd = wave_sum(rgd);
-      rgd2 = wave_sum(rgd2);
+      {
+        // F' in LDS is no longer read: its space is this wave's scratch
+        const double part[5] = {s1, s2, rg, rgd, rgd2};
+        double *tot = reinterpret_cast<double *>(sF) + 512;
+        wave_sum_lds<5>(part, reinterpret_cast<double *>(sF), tot, lane);
+        s1 = tot[0];
+        s2 = tot[1];
+        rg = tot[2];
+        rgd = tot[3];
+        rgd2 = tot[4];
+      }
       const double sp = sSp[a];
       const double dmu = (rgd - s1 * rg) / (sp * sp);
       const double dsig = (rgd2 - s2 * rg) / (sp * sp * sp);
@@ -472,6 +479,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
         }
 #pragma unroll
         for (int t = 0; t < kTB; ++t) {
+          if (mb + t >= T) break;  // wave uniform
           const float gk = K[mb + t];
 #pragma unroll
           for (int i = 0; i < kNPL; ++i) fb[i] = fmaf(gk, w[i + t], fb[i]);

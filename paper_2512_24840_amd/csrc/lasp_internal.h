@@ -204,12 +204,6 @@ __device__ inline T wave_reduce_scatter(T (&v)[N], int lane) {
   return r;
 }
 
-template <typename T>
-__device__ inline T wave_sum(T x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
 
 // Makes the compiler treat x as a new value: computations from x after this
 // point are not merged with the same computations before it (which would
@@ -227,11 +221,6 @@ __device__ inline double read_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ inline float wave_min(float x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
-  return x;
-}
 
 template <int N>
 struct Pow2 {
@@ -277,6 +266,76 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sum over each aligned group of eight lanes, returned in all eight, by DPP
+// lane moves (no LDS round trip): swap neighbours, swap pairs within a
+// quad, then mirror within the half row, which pairs the group's two quads.
+// The additions form the same tree in every lane, so all eight agree.
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ inline int dpp_mov(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <typename T>
+__device__ inline T group8_sum(T v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  return v;
+}
+
+__device__ inline int read_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Sum over the wave, the same value in every lane: eight-lane groups, then
+// the row mirror pairs the two groups of each 16-lane row, then the four
+// row sums are read through scalar registers and added in a fixed order.
+template <typename T>
+__device__ inline T wave_sum(T x) {
+  x = group8_sum(x);
+  x += dpp_mov<0x140>(x);  // row_mirror
+  return (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
+}
+
+__device__ inline float wave_min(float x) {
+  x = fminf(x, dpp_mov<0xB1>(x));
+  x = fminf(x, dpp_mov<0x4E>(x));
+  x = fminf(x, dpp_mov<0x141>(x));
+  x = fminf(x, dpp_mov<0x140>(x));
+  return fminf(fminf(read_lane(x, 0), read_lane(x, 16)), fminf(read_lane(x, 32), read_lane(x, 48)));
+}
+
+// Sum of NV per-lane doubles over one wave through LDS (no workgroup
+// barrier: any single wave may call it).  scratch holds 8 x 64 doubles;
+// out[0..NV) (LDS) is valid in every lane after the call.  Deterministic.
+template <int NV>
+__device__ inline void wave_sum_lds(const double (&acc)[NV], double *scratch, double *out,
+                                    int lane) {
+  const int tt = lane >> 3, part = lane & 7;
+#pragma unroll
+  for (int c = 0; c < (NV + 7) / 8; ++c) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) scratch[t * 64 + lane] = (8 * c + t < NV) ? acc[(8 * c + t) % NV] : 0.0;
+    wave_lds_sync();
+    const double *row = scratch + tt * 64 + 8 * part;
+    double v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));
+    v = group8_sum(v);
+    if (part == 0 && 8 * c + tt < NV) out[8 * c + tt] = v;
+    wave_lds_sync();
+  }
+}
+
 // Sum of NV per-lane doubles over the workgroup through LDS: eight values at
 // a time are transposed through scratch[wave][8][64] (one wave's region is
 // 4 KB), each group of eight lanes adds one value's 64 partials, then the
@@ -294,9 +353,7 @@ __device__ inline void block_sum_lds(const double (&acc)[NV], double *scratch, d
     wave_lds_sync();
     const double *row = sc + tt * 64 + 8 * part;
     double v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
+    v = group8_sum(v);
     if (part == 0) red[wave * 64 + 8 * c + tt] = v;
     wave_lds_sync();
   }
