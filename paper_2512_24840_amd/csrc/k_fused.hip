@@ -206,39 +206,69 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   }
 
   // ---- Eq. 6 moments in FP64: nu_l = sum W F''^2 T_l, r_n = sum W F'' o T_n
+  //      (two passes over the pixels: fewer accumulators live at once)
   {
-    double acc[NMOM];
-#pragma unroll
-    for (int k = 0; k < NMOM; ++k) acc[k] = 0.0;
     const double two_over_p = 2.0 / (double)P;
+    double *scr = reinterpret_cast<double *>(sF + L.gb_off);
+    {
 #pragma unroll
-    for (int i = 0; i < kNPL; ++i) {
-      const double x = fma((double)(j0 + i), two_over_p, -1.0);
-      const double f = (double)fpp[i];
-      const double wf = (double)ow[i].y * f;
-      const double y = wf * f;
-      const double z = wf * (double)ow[i].x;
-      double tm = 1.0, tc = x;
-      acc[0] += y;
-      acc[1] = fma(y, x, acc[1]);
-      acc[NNU] += z;
-      acc[NNU + 1] = fma(z, x, acc[NNU + 1]);
-      const double x2 = x + x;
-#pragma unroll
-      for (int l = 2; l < NNU; ++l) {
-        const double tn = fma(x2, tc, -tm);
-        acc[l] = fma(y, tn, acc[l]);
-        if (l < ND) acc[NNU + l] = fma(z, tn, acc[NNU + l]);
-        tm = tc;
-        tc = tn;
+      for (int i = 0; i < kNPL; ++i) {
+        opaque(fpp[i]);
+        opaque(ow[i]);
       }
-      // one pixel at a time: keeps the scheduler from hoisting every pixel's
-      // FP64 operands (register pressure)
-      __builtin_amdgcn_sched_barrier(0);
+      double acc[NNU];
+#pragma unroll
+      for (int k = 0; k < NNU; ++k) acc[k] = 0.0;
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i) {
+        const double x = fma((double)(j0 + i), two_over_p, -1.0);
+        const double f = (double)fpp[i];
+        const double y = (double)ow[i].y * f * f;
+        double tm = 1.0, tc = x;
+        acc[0] += y;
+        acc[1] = fma(y, x, acc[1]);
+        const double x2 = x + x;
+#pragma unroll
+        for (int l = 2; l < NNU; ++l) {
+          const double tn = fma(x2, tc, -tm);
+          acc[l] = fma(y, tn, acc[l]);
+          tm = tc;
+          tc = tn;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      block_sum_lds<NW, NNU>(acc, scr, sRed, sMom, lane, wave);
     }
-    // the g-bar row is not live yet: use it as transpose scratch, then clear it
-    block_sum_lds<NW, NMOM>(acc, reinterpret_cast<double *>(sF + L.gb_off), sRed, sMom, lane,
-                            wave);
+    {
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i) {
+        opaque(fpp[i]);
+        opaque(ow[i]);
+      }
+      int jb = j0;
+      opaque(jb);
+      double acc[ND];
+#pragma unroll
+      for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i) {
+        const double x = fma((double)(jb + i), two_over_p, -1.0);
+        const double z = (double)ow[i].y * (double)fpp[i] * (double)ow[i].x;
+        double tm = 1.0, tc = x;
+        acc[0] += z;
+        acc[1] = fma(z, x, acc[1]);
+        const double x2 = x + x;
+#pragma unroll
+        for (int l = 2; l < ND; ++l) {
+          const double tn = fma(x2, tc, -tm);
+          acc[l] = fma(z, tn, acc[l]);
+          tm = tc;
+          tc = tn;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      block_sum_lds<NW, ND>(acc, scr, sRed, sMom + NNU, lane, wave);
+    }
     for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
   }
 
