@@ -54,6 +54,8 @@ def parse(argv=None):
     p.add_argument("--duration", type=float, default=20.0, help="serving: seconds of arrivals")
     p.add_argument("--rate", type=float, default=20000.0, help="serving: spectra/s offered")
     p.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32")
+    p.add_argument("--no-extra-legs", action="store_true",
+                   help="time only the headline grouped fit (no early-stop or LM legs)")
     p.add_argument("--lm-iters", type=int, default=30,
                    help="Levenberg-Marquardt iterations (at most) of the plain LM leg")
     p.add_argument("--polish-adam-steps", type=int, default=100,
@@ -279,24 +281,27 @@ def main():
 
     # the same group with the per-spectrum stopping rules of the optimisation
     # stage (window 50, threshold 1e-5 on sqrt(chi2 / n_eff)), timed alone
-    es_kw = dict(kw, stop_window=args.stop_window, stop_tol=args.stop_tol)
-    res_es = lasp.fit_group(obs, ivar, grid, bas, init, args.adam_steps, **es_kw)
-    torch.cuda.synchronize()
+    extra = not args.no_extra_legs
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    lasp.fit_group(obs, ivar, grid, bas, init, args.adam_steps, out=res_es, **es_kw)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_es = e0.elapsed_time(e1) / 1e3
-    steps_es = res_es.steps.cpu().numpy()
-    status_es = res_es.status.cpu().numpy()
-    params_es = res_es.params.cpu().numpy().astype(np.float64)
+    if extra:
+        es_kw = dict(kw, stop_window=args.stop_window, stop_tol=args.stop_tol)
+        res_es = lasp.fit_group(obs, ivar, grid, bas, init, args.adam_steps, **es_kw)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        lasp.fit_group(obs, ivar, grid, bas, init, args.adam_steps, out=res_es, **es_kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_es = e0.elapsed_time(e1) / 1e3
+        steps_es = res_es.steps.cpu().numpy()
+        status_es = res_es.status.cpu().numpy()
+        params_es = res_es.params.cpu().numpy().astype(np.float64)
 
     # Levenberg-Marquardt legs: a plain LM fit from the start point, and a
     # short Adam run polished by LM (both with the covariance)
     lm_legs = {}
-    for leg, (n_adam, n_lm) in (("lm", (0, args.lm_iters)),
-                                ("adam_lm", (args.polish_adam_steps, args.polish_iters))):
+    for leg, (n_adam, n_lm) in ((("lm", (0, args.lm_iters)),
+                                 ("adam_lm", (args.polish_adam_steps, args.polish_iters)))
+                                if extra else ()):
         res_lm = lasp.fit_group(obs, ivar, grid, bas, init, n_adam, polish_iters=n_lm, **kw)
         torch.cuda.synchronize()
         e0.record(stream)
@@ -351,7 +356,9 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "status_flagged": int((status != 0).sum()),
-        "early_stop": {
+    }
+    if extra:
+        out["early_stop"] = {
             "value": B / t_es, "unit": "spectra/s", "ms_per_group_fit": t_es * 1e3,
             "window": args.stop_window, "tol": args.stop_tol, "max_steps": args.adam_steps,
             "steps_mean": float(steps_es.mean()), "steps_p50": float(np.median(steps_es)),
@@ -359,8 +366,7 @@ def main():
             "stopped_flat": int(((status_es & lasp.ST_STOP_FLAT) != 0).sum()),
             "stopped_rising": int(((status_es & lasp.ST_STOP_RISING) != 0).sum()),
             "not_converged": int(((status_es & lasp.ST_NOT_CONVERGED) != 0).sum()),
-        },
-    }
+        }
     for leg, d in lm_legs.items():
         out[leg] = {"value": B / d["t"], "unit": "spectra/s", "ms_per_group_fit": d["t"] * 1e3,
                     "adam_steps": d["adam_steps"], "max_lm_iters": d["lm_iters"],
@@ -400,11 +406,12 @@ def main():
                 "n": n, "matched": int(np.all(e <= FIT_TOL, axis=1).sum()),
                 "max_abs_err": {k: float(v) for k, v in zip(("teff_K", "logg", "feh", "rv_kms"),
                                                             e.max(axis=0))}}
-        err_es = np.abs(params_es[:n] - refp)[:, :4]
-        out["early_stop"]["oracle_match"] = {
-            "n": n, "matched": int(np.all(err_es <= FIT_TOL, axis=1).sum()),
-            "max_abs_err": {k: float(v) for k, v in zip(("teff_K", "logg", "feh", "rv_kms"),
-                                                        err_es.max(axis=0))}}
+        if extra:
+            err_es = np.abs(params_es[:n] - refp)[:, :4]
+            out["early_stop"]["oracle_match"] = {
+                "n": n, "matched": int(np.all(err_es <= FIT_TOL, axis=1).sum()),
+                "max_abs_err": {k: float(v) for k, v in zip(("teff_K", "logg", "feh", "rv_kms"),
+                                                            err_es.max(axis=0))}}
     print(json.dumps(out), flush=True)
 
 
