@@ -88,8 +88,12 @@ def _load():
         lib.orc_stop_step.restype = ctypes.c_int
         dd = ctypes.c_double
         lib.orc_adam_fit.argtypes = [cp, fp, fp, fp, dp, ctypes.c_int, dd, dd, dd, dd,
-                                     ctypes.c_int, dd, dp, ip, ip, dp]
+                                     ctypes.c_int, dd, ctypes.c_int, ctypes.c_int, dp, ip, ip, dp,
+                                     ctypes.POINTER(ctypes.c_uint8)]
         lib.orc_adam_fit.restype = ctypes.c_int
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        lib.orc_clean.argtypes = [ctypes.c_int, fp, fp, dp, ctypes.c_double, u8p, dp, ip]
+        lib.orc_clean.restype = ctypes.c_int
         lib.orc_covariance.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -258,9 +262,10 @@ def stop_step(ell, n_max, window, tol):
 
 
 def adam_fit(cfg: Config, obs, ivar, basis, u0, n_max=500, lr=1e-2, betas=(0.9, 0.999),
-             eps=1e-8, window=0, tol=1e-5):
+             eps=1e-8, window=0, tol=1e-5, clean_every=0, clean_max=11):
     """FP64 Adam on chi2/n_eff from normalised start u0, with the stopping
-    rules when window > 0.  Returns u, steps, rule, loss history, params."""
+    rules when window > 0 and the Clean mask updates when clean_every > 0.
+    Returns u, steps, rule, loss history, final mask (keep) and params."""
     lib = _load()
     obs, ivar, basis = _f32(obs), _f32(ivar), _f32(basis)
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
@@ -268,11 +273,29 @@ def adam_fit(cfg: Config, obs, ivar, basis, u0, n_max=500, lr=1e-2, betas=(0.9, 
     ell = np.empty(n_max + 1)
     steps = ctypes.c_int()
     rule = ctypes.c_int()
+    keep = np.empty(cfg.n_pix, dtype=np.uint8)
     lib.orc_adam_fit(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u0), int(n_max),
                      float(lr), float(betas[0]), float(betas[1]), float(eps), int(window),
-                     float(tol), _d(u), ctypes.byref(steps), ctypes.byref(rule), _d(ell))
+                     float(tol), int(clean_every), int(clean_max), _d(u), ctypes.byref(steps),
+                     ctypes.byref(rule), _d(ell), keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
     return dict(u=u, steps=steps.value, rule=rule.value, ell=ell[:steps.value + 1].copy(),
-                params=cfg.physical(u))
+                keep=keep, params=cfg.physical(u))
+
+
+def clean_mask(obs, ivar, model, f_shift):
+    """Clean outlier mask of one spectrum: keep (1) / masked (0) per pixel,
+    the number of masked valid pixels, the accepted k and the D passes."""
+    lib = _load()
+    obs, ivar = _f32(obs), _f32(ivar)
+    model = np.ascontiguousarray(model, dtype=np.float64)
+    n = obs.shape[0]
+    keep = np.empty(n, dtype=np.uint8)
+    k = ctypes.c_double()
+    it = ctypes.c_int()
+    masked = lib.orc_clean(int(n), _f(obs), _f(ivar), _d(model), float(f_shift),
+                           keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(k),
+                           ctypes.byref(it))
+    return dict(keep=keep, masked=masked, k=k.value, d_iters=it.value)
 
 
 def adam_fit_many(cfg: Config, obs, ivar, basis, init_phys, threads=None, **kw):

@@ -635,6 +635,9 @@ int orc_covariance(const orc_cfg *cfg, const float *obs, const float *ivar, cons
  * t at which rule 2 or 3 holds, with the rule in *rule; otherwise n_max
  * with *rule = 1.  Rule 2 is tested first.
  */
+int orc_clean(int n, const float *obs, const float *ivar, const double *model, double f_shift,
+              unsigned char *keep, double *k_used, int *d_iters);
+
 int orc_stop_rule(const double *ell, int t, int W, double tol) {
   if (W <= 0 || t < W) return 0;
   if (fabs(ell[t - W] - ell[t]) < tol) return 2;
@@ -663,21 +666,39 @@ int orc_stop_step(const double *ell, int n_max, int W, double tol, int *rule) {
  * first and second moment estimates, bias corrected with beta^t, and eps is
  * added to the square root of the corrected v.  With W > 0 the stopping
  * rules above end the fit (the step that would follow is not taken).
+ * With clean_every > 0 the Clean strategy of stage 8 updates the mask after
+ * every clean_every steps, at most clean_max times: the model at the
+ * current parameters gives the residuals, orc_clean gives the mask (f_shift
+ * 0.5 at the first update, 0.2 after), and masked pixels get weight zero
+ * from then on (each update starts from the input weights).
  * Outputs: u_out[5], steps taken, rule (1, 2, 3), and optionally
- * ell_out[0..steps] (n_max + 1 entries).  Returns 0.
+ * ell_out[0..steps] (n_max + 1 entries) and keep_out[P] (final mask).
+ * Returns 0.
  */
 int orc_adam_fit(const orc_cfg *cfg, const float *obs, const float *ivar, const float *basis,
                  const double *u0, int n_max, double lr, double beta1, double beta2, double eps,
-                 int W, double tol, double *u_out, int *steps_out, int *rule_out,
-                 double *ell_out) {
+                 int W, double tol, int clean_every, int clean_max, double *u_out,
+                 int *steps_out, int *rule_out, double *ell_out, unsigned char *keep_out) {
   double u[ORC_NP], m[ORC_NP] = {0, 0, 0, 0, 0}, v[ORC_NP] = {0, 0, 0, 0, 0};
   memcpy(u, u0, sizeof(u));
+  const int P = cfg->n_pix;
   double *ell = (double *)malloc(sizeof(double) * (size_t)(n_max + 1));
-  int t = 0, rule = 1;
+  float *iv = (float *)malloc(sizeof(float) * (size_t)P);
+  double *model = (double *)malloc(sizeof(double) * (size_t)P);
+  unsigned char *keep = (unsigned char *)malloc((size_t)P);
+  memcpy(iv, ivar, sizeof(float) * (size_t)P);
+  memset(keep, 1, (size_t)P);
+  int t = 0, rule = 1, updates = 0;
   for (;; ++t) {
+    if (clean_every > 0 && t > 0 && t % clean_every == 0 && updates < clean_max) {
+      orc_eval(cfg, obs, ivar, basis, u, NULL, NULL, NULL, model, NULL, NULL, NULL, NULL, NULL);
+      orc_clean(P, obs, ivar, model, updates == 0 ? 0.5 : 0.2, keep, NULL, NULL);
+      for (int j = 0; j < P; ++j) iv[j] = keep[j] ? ivar[j] : 0.0f;
+      ++updates;
+    }
     double chi2 = 0.0, g[ORC_NP];
     int n_eff = 0;
-    orc_eval(cfg, obs, ivar, basis, u, NULL, NULL, NULL, NULL, &chi2, &n_eff, g, NULL, NULL);
+    orc_eval(cfg, obs, iv, basis, u, NULL, NULL, NULL, NULL, &chi2, &n_eff, g, NULL, NULL);
     ell[t] = n_eff > 0 ? sqrt(chi2 / (double)n_eff) : 0.0;
     if (t == n_max) break;
     int r = orc_stop_rule(ell, t, W, tol);
@@ -698,6 +719,119 @@ int orc_adam_fit(const orc_cfg *cfg, const float *obs, const float *ivar, const 
   if (steps_out) *steps_out = t;
   if (rule_out) *rule_out = rule;
   if (ell_out) memcpy(ell_out, ell, sizeof(double) * (size_t)(t + 1));
+  if (keep_out) memcpy(keep_out, keep, (size_t)P);
   free(ell);
+  free(iv);
+  free(model);
+  free(keep);
   return 0;
+}
+
+/*
+ * Clean outlier mask of one spectrum (Section 2.2, step 6, the three-step
+ * clipping of the Clean strategy), from its residual eps = o - m against a
+ * model m and its valid pixels (W > 0).  Readings: sigma is the sample
+ * standard deviation (n - 1) of eps over the valid pixels; sigma' in the
+ * third step uses the valid pixels kept by the first two steps; the flux
+ * gradient G_j = max(|m_j - m_{j-1}|, |m_j - m_{j+1}|) uses the neighbour
+ * that exists at the ends of the spectrum; only valid pixels are tested and
+ * only valid pixels seed a neighbour test.
+ *   B: |eps_j| - f G_j > k sigma masks j; k = 3, relaxed to 4, 5, 7 while
+ *      more than 3 % of the valid pixels would be masked.
+ *   C: a neighbour j' of a B outlier with |eps_j'| - f G_j' > 2 sigma.
+ *   D: a neighbour j' of an outlier j (B, C or D) with eps_j eps_j' > 0,
+ *      |eps_j'| <= |eps_j| and |eps_j'| - f G_j' > sigma'; repeated until D
+ *      does not change, at most 20 times.
+ * keep[j] = 1 if kept (A_j = B_j C_j D_j = 1), 0 if masked; invalid pixels
+ * are reported as kept (they carry no weight).  Returns the number of
+ * masked valid pixels; *k_used gets the accepted k, *d_iters the D passes.
+ */
+int orc_clean(int n, const float *obs, const float *ivar, const double *model, double f_shift,
+              unsigned char *keep, double *k_used, int *d_iters) {
+  unsigned char *valid = (unsigned char *)malloc((size_t)n);
+  unsigned char *B = (unsigned char *)malloc((size_t)n);
+  unsigned char *C = (unsigned char *)malloc((size_t)n);
+  unsigned char *D = (unsigned char *)malloc((size_t)n);
+  unsigned char *Dn = (unsigned char *)malloc((size_t)n);
+  double *eps = (double *)malloc(sizeof(double) * (size_t)n);
+  double *G = (double *)malloc(sizeof(double) * (size_t)n);
+  int nv = 0;
+  for (int j = 0; j < n; ++j) {
+    valid[j] = isfinite(obs[j]) && isfinite(ivar[j]) && ivar[j] > 0.0f;
+    eps[j] = (double)obs[j] - model[j];
+    double gl = j > 0 ? fabs(model[j] - model[j - 1]) : 0.0;
+    double gr = j + 1 < n ? fabs(model[j] - model[j + 1]) : 0.0;
+    G[j] = gl > gr ? gl : gr;
+    nv += valid[j];
+    B[j] = C[j] = D[j] = 1;
+  }
+  double mean = 0.0, var = 0.0;
+  for (int j = 0; j < n; ++j)
+    if (valid[j]) mean += eps[j];
+  mean = nv > 0 ? mean / nv : 0.0;
+  for (int j = 0; j < n; ++j)
+    if (valid[j]) var += (eps[j] - mean) * (eps[j] - mean);
+  const double sigma = nv > 1 ? sqrt(var / (nv - 1)) : 0.0;
+  /* step B with the relaxed thresholds */
+  static const double ks[4] = {3.0, 4.0, 5.0, 7.0};
+  double k = 7.0;
+  for (int q = 0; q < 4; ++q) {
+    int cnt = 0;
+    for (int j = 0; j < n; ++j)
+      if (valid[j] && fabs(eps[j]) - f_shift * G[j] > ks[q] * sigma) ++cnt;
+    if (cnt <= 0.03 * nv || q == 3) {
+      k = ks[q];
+      break;
+    }
+  }
+  for (int j = 0; j < n; ++j)
+    B[j] = !(valid[j] && fabs(eps[j]) - f_shift * G[j] > k * sigma);
+  /* step C */
+  for (int j = 0; j < n; ++j) {
+    if (B[j]) continue;
+    for (int s = -1; s <= 1; s += 2) {
+      int jp = j + s;
+      if (jp < 0 || jp >= n || !valid[jp]) continue;
+      if (fabs(eps[jp]) - f_shift * G[jp] > 2.0 * sigma) C[jp] = 0;
+    }
+  }
+  /* sigma' over the valid pixels kept by B and C */
+  int n2 = 0;
+  double mean2 = 0.0, var2 = 0.0;
+  for (int j = 0; j < n; ++j)
+    if (valid[j] && B[j] && C[j]) {
+      mean2 += eps[j];
+      ++n2;
+    }
+  mean2 = n2 > 0 ? mean2 / n2 : 0.0;
+  for (int j = 0; j < n; ++j)
+    if (valid[j] && B[j] && C[j]) var2 += (eps[j] - mean2) * (eps[j] - mean2);
+  const double sigma2 = n2 > 1 ? sqrt(var2 / (n2 - 1)) : 0.0;
+  /* step D, repeated until it does not change */
+  int it = 0;
+  for (; it < 20; ++it) {
+    memcpy(Dn, D, (size_t)n);
+    for (int j = 0; j < n; ++j) {
+      if (!valid[j] || (B[j] && C[j] && D[j])) continue;
+      for (int s = -1; s <= 1; s += 2) {
+        int jp = j + s;
+        if (jp < 0 || jp >= n || !valid[jp]) continue;
+        if (eps[j] * eps[jp] > 0.0 && fabs(eps[jp]) <= fabs(eps[j]) &&
+            fabs(eps[jp]) - f_shift * G[jp] > sigma2)
+          Dn[jp] = 0;
+      }
+    }
+    int changed = memcmp(Dn, D, (size_t)n) != 0;
+    memcpy(D, Dn, (size_t)n);
+    if (!changed) break;
+  }
+  int masked = 0;
+  for (int j = 0; j < n; ++j) {
+    keep[j] = !(valid[j] && !(B[j] && C[j] && D[j]));
+    masked += !keep[j];
+  }
+  if (k_used) *k_used = k;
+  if (d_iters) *d_iters = it;
+  free(valid); free(B); free(C); free(D); free(Dn); free(eps); free(G);
+  return masked;
 }
