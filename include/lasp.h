@@ -112,6 +112,15 @@ extern "C" {
  *                  (LASP_ST_POLISH_LIMIT if the iteration limit came first).  The paper proposes adding curvature
  *                  information to its Adam stage (Section 5); n_steps = 0
  *                  with polish_iters > 0 is a plain LM fit.
+ *  clean_every, clean_max  the Clean strategy of Section 2.2 (steps 6 and 8):
+ *                  after every clean_every Adam steps (at most clean_max
+ *                  times; the paper's 30 and 11) the model at the current
+ *                  parameters gives each spectrum's residual, the three-step
+ *                  clipping of lasp_clean_mask (f_shift 0.5 at the first
+ *                  update, 0.2 after) gives its mask, and clipped pixels get
+ *                  zero weight until the next update.  0 = No Clean.
+ *  out_mask        optional device uint8 [n_spec][n_pix]: the last Clean
+ *                  mask (1 kept, 0 clipped; all 1 if no update ran).
  */
 typedef struct lasp_opts {
   int32_t n_spec;
@@ -134,13 +143,17 @@ typedef struct lasp_opts {
   float stop_tol;
   int32_t *out_steps;
   int32_t polish_iters;
+  int32_t clean_every;
+  int32_t clean_max;
+  uint8_t *out_mask;
 } lasp_opts;
 
 /* Defaults: n_basis 20, margin 64, degree 10, FP32, box
  * lo = (log10 4000, 1, -2.5, -300, 50), hi = (log10 8000, 5, 0.5, 300, 150),
  * lr 1e-2, betas (0.9, 0.999), eps 1e-8, weight_quantile 0.5, no arms,
  * null stream, no status/chi2 outputs, stopping rules off (stop_window 0,
- * stop_tol 1e-5), no out_steps, no polish.  n_spec and n_pix are set to 0. */
+ * stop_tol 1e-5), no out_steps, no polish, No Clean (clean_every 0,
+ * clean_max 11), no out_mask.  n_spec and n_pix are set to 0. */
 void lasp_default_opts(lasp_opts *opts);
 
 /*
@@ -179,6 +192,28 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid,
                  const float *basis, const float *u, float *out_model, double *out_chi2,
                  float *out_J, int32_t *out_neff, float *out_grad, float *out_jac,
                  double *out_cov, const lasp_opts *opts);
+
+/*
+ * Clean outlier mask (Section 2.2, step 6) of each spectrum from its
+ * residual eps = obs - model, in three steps:
+ *   B  |eps_j| - f_shift G_j > k sigma, with G_j = max |model_j - model_{j+-1}|
+ *      and k = 3, relaxed to 4, 5, 7 while more than 3 % of the valid
+ *      pixels would be clipped;
+ *   C  a neighbour of a B outlier with |eps| - f_shift G > 2 sigma;
+ *   D  a neighbour j' of an outlier j with eps_j eps_j' > 0,
+ *      |eps_j'| <= |eps_j| and |eps_j'| - f_shift G_j' > sigma', repeated
+ *      until it does not change (at most 20 passes).
+ * sigma is the sample standard deviation of eps over the valid pixels
+ * (finite obs and ivar, ivar > 0) and sigma' over those kept by B and C.
+ * Only valid pixels are clipped or seed a neighbour test.
+ *   obs, ivar, model  [B][P] float (device)
+ *   keep              [B][P] uint8 (device): 1 kept (or invalid), 0 clipped
+ *   n_masked          optional [B] int32 (device): clipped valid pixels
+ * Uses opts->n_spec, n_pix, margin (for the pixel layout) and stream.
+ */
+int lasp_clean_mask(const float *obs, const float *ivar, const float *model, float f_shift,
+                    uint8_t *keep, int32_t *n_masked, const double *wave_grid,
+                    const lasp_opts *opts);
 
 /*
  * Kernel timing for benchmarks.  lasp_profile_enable(mask) clears the

@@ -21,6 +21,7 @@ from .lasp import (  # noqa: F401
     ST_SINGULAR,
     ST_STOP_FLAT,
     ST_STOP_RISING,
+    clean_mask,
     fit_group,
     forward,
     library_path,

@@ -35,6 +35,8 @@ struct Workspace {
   int device = 0;
   hipStream_t stream = nullptr;
   size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0, cap_hist = 0, cap_lm = 0;
+  size_t cap_model = 0;
+  float *model = nullptr;  // [B][P] model for the Clean updates
   State s{};
   lasp::LmState lm{};
 };
@@ -68,6 +70,9 @@ void free_ws(Workspace *w) {
                    l.need_jac, l.flags};
   for (void *p : lptrs)
     if (p) (void)hipFree(p);
+  if (w->model) (void)hipFree(w->model);
+  w->model = nullptr;
+  w->cap_model = 0;
   w->s = State{};
   w->lm = lasp::LmState{};
   w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = w->cap_hist = w->cap_lm = 0;
@@ -215,6 +220,8 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
     return fail(LASP_E_ARG, "stop_tol must be finite and >= 0");
   if (o->polish_iters < 0 || o->polish_iters > 1000)
     return fail(LASP_E_ARG, "polish_iters must be in [0, 1000]");
+  if (o->clean_every < 0 || o->clean_max < 0)
+    return fail(LASP_E_ARG, "clean_every and clean_max must be >= 0");
   if (!wave_grid) return fail(LASP_E_ARG, "wave_grid is NULL");
 
   const int P = o->n_pix;
@@ -380,6 +387,7 @@ void lasp_default_opts(lasp_opts *o) {
   o->weight_quantile = 0.5f;
   o->stop_window = 0;
   o->stop_tol = 1e-5f;
+  o->clean_max = 11;
 }
 
 const char *lasp_last_error(void) { return g_err.c_str(); }
@@ -435,8 +443,28 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   Workspace *w = nullptr;
   const int W = opts->stop_window;
   const int polish = opts->polish_iters;
+  const int ce = opts->clean_every, cm = opts->clean_max;
   rc = get_workspace(g, (out_cov || polish) ? 4 : 1, W, st, &w, polish > 0);
   if (rc) return rc;
+  if (ce > 0) {
+    const size_t need = (size_t)g.B * g.P;
+    if (need > w->cap_model) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e == hipSuccess && w->model) e = hipFree(w->model);
+      w->model = nullptr;
+      w->cap_model = 0;
+      if (e == hipSuccess) e = hipMalloc((void **)&w->model, need * sizeof(float));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LASP_E_NOMEM, std::string("Clean model buffer: ") + hipGetErrorString(e));
+      }
+      w->cap_model = need;
+    }
+    if (opts->out_mask) {
+      hipError_t e = hipMemsetAsync(opts->out_mask, 1, (size_t)g.B * g.P, st);
+      if (e != hipSuccess) return dev_fail(e, "out_mask init");
+    }
+  }
   State s = w->s;
   if (W == 0) s.target = nullptr;  // every spectrum takes n_steps steps
   const int bf16 = opts->precision == LASP_PREC_BF16X3;
@@ -454,6 +482,12 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
     {
       LASP_TIMED(LASP_K_INTERP_FWD, st);
       LASP_CHECK(lasp::launch_interp_fwd(g, s, 0, bf16, st), "interpolator contraction");
+    }
+    if (ce > 0 && it > 0 && it % ce == 0 && it / ce <= cm) {
+      // Clean update: residual of the current model, new mask and weights
+      LASP_CHECK(lasp::launch_fused(g, s, 0, w->model, st), "fused pass (model)");
+      lasp::CleanArgs ca{obs, ivar, w->model, it == ce ? 0.5f : 0.2f, opts->out_mask, nullptr, s};
+      LASP_CHECK(lasp::launch_clean(g, ca, st), "Clean mask");
     }
     {
       LASP_TIMED(LASP_K_FUSED, st);
@@ -505,6 +539,23 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
                                      opts->out_chi2, opts->out_steps, st),
                "finalize");
   }
+  return LASP_OK;
+}
+
+int lasp_clean_mask(const float *obs, const float *ivar, const float *model, float f_shift,
+                    uint8_t *keep, int32_t *n_masked, const double *wave_grid,
+                    const lasp_opts *opts) {
+  g_err.clear();
+  Geometry g;
+  int rc = make_geometry(opts, wave_grid, &g);
+  if (rc) return rc;
+  if (!obs || !ivar || !model || !keep)
+    return fail(LASP_E_ARG, "obs, ivar, model and keep are required");
+  if (!(f_shift >= 0.f) || !std::isfinite(f_shift)) return fail(LASP_E_ARG, "f_shift must be >= 0");
+  if (g.B == 0) return LASP_OK;
+  hipStream_t st = (hipStream_t)opts->stream;
+  lasp::CleanArgs ca{obs, ivar, model, f_shift, keep, n_masked, State{}};
+  LASP_CHECK(lasp::launch_clean(g, ca, st), "Clean mask");
   return LASP_OK;
 }
 

@@ -98,6 +98,20 @@ struct LmState {
   int *flags;          // [B] kLmDone
 };
 
+// Inputs and outputs of the Clean mask kernel.  obs, ivar and model are
+// [B][P] row-major in the units of obs.  With s.ow set, the kernel writes
+// the new weights into the fused pass's (o/w, W w^2) array and n_eff; with
+// s.target set, stopped spectra are skipped.
+struct CleanArgs {
+  const float *obs;
+  const float *ivar;
+  const float *model;
+  float f_shift;
+  uint8_t *keep_out;   // optional [B][P]: 1 kept, 0 clipped
+  int32_t *masked_out; // optional [B]: clipped valid pixels
+  State s;             // ow, wscale, neff, t, target (others unused)
+};
+
 struct AdamCfg {
   float lr, beta1, beta2, eps;
   int stop_window;  // 0: fixed step count
@@ -139,6 +153,7 @@ hipError_t launch_lm_init(const Geometry &g, const LmState &lm, hipStream_t st);
 hipError_t launch_lm_solve(const Geometry &g, const State &s, const LmState &lm, hipStream_t st);
 hipError_t launch_lm_accept(const Geometry &g, const State &s, const LmState &lm, int last,
                             hipStream_t st);
+hipError_t launch_clean(const Geometry &g, const CleanArgs &a, hipStream_t st);
 bool fused_supported(int block, int nd);
 size_t fused_smem_bytes(const Geometry &g);
 

@@ -37,7 +37,7 @@ N_PAR = 5
 EXPORTED = ("lasp_default_opts", "lasp_fit_group", "lasp_forward", "lasp_last_error",
             "lasp_release", "lasp_profile_enable", "lasp_profile_read", "lasp_pool_slot_bytes",
             "lasp_pool_create", "lasp_pool_load", "lasp_pool_step", "lasp_pool_progress",
-            "lasp_pool_finish", "lasp_pool_destroy")
+            "lasp_pool_finish", "lasp_pool_destroy", "lasp_clean_mask")
 KERNELS = ("prepare", "interp_fwd", "fused", "interp_bwd", "cov", "finalize")
 
 
@@ -72,6 +72,9 @@ class LaspOpts(ctypes.Structure):
         ("stop_tol", ctypes.c_float),
         ("out_steps", ctypes.c_void_p),
         ("polish_iters", ctypes.c_int32),
+        ("clean_every", ctypes.c_int32),
+        ("clean_max", ctypes.c_int32),
+        ("out_mask", ctypes.c_void_p),
     ]
 
 
@@ -121,6 +124,9 @@ def load() -> ctypes.CDLL:
         lib.lasp_pool_progress.restype = ctypes.c_int
         lib.lasp_pool_finish.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         lib.lasp_pool_finish.restype = ctypes.c_int
+        lib.lasp_clean_mask.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, vp,
+                                        ctypes.POINTER(LaspOpts)]
+        lib.lasp_clean_mask.restype = ctypes.c_int
         lib.lasp_pool_destroy.argtypes = [vp]
         lib.lasp_pool_destroy.restype = ctypes.c_int
         _lib = lib
@@ -156,7 +162,8 @@ class Arms:
 
 def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
               betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5, arms: Arms | None = None,
-              box=None, stream=None, stop_window=0, stop_tol=1e-5, polish_iters=0) -> LaspOpts:
+              box=None, stream=None, stop_window=0, stop_tol=1e-5, polish_iters=0,
+              clean_every=0, clean_max=11) -> LaspOpts:
     o = LaspOpts()
     load().lasp_default_opts(ctypes.byref(o))
     o.n_spec, o.n_pix, o.margin, o.degree = int(n_spec), int(n_pix), int(margin), int(degree)
@@ -165,6 +172,7 @@ def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
     o.weight_quantile = float(weight_quantile)
     o.stop_window, o.stop_tol = int(stop_window), float(stop_tol)
     o.polish_iters = int(polish_iters)
+    o.clean_every, o.clean_max = int(clean_every), int(clean_max)
     if box is not None:
         lo, hi = box
         for t in range(5):
@@ -193,16 +201,19 @@ class FitResult:
     status: torch.Tensor          # [B] int32 (LASP_ST_* bits)
     chi2: torch.Tensor            # [B] float64
     steps: torch.Tensor | None = None  # [B] int32 Adam steps taken
+    mask: torch.Tensor | None = None   # [B, P] uint8 last Clean mask (1 kept)
 
 
 def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=False,
               margin=64, degree=10, precision="fp32", lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
               weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
-              stop_window=0, stop_tol=1e-5, polish_iters=0,
-              out: FitResult | None = None) -> FitResult:
+              stop_window=0, stop_tol=1e-5, polish_iters=0, clean_every=0, clean_max=11,
+              want_mask=False, out: FitResult | None = None) -> FitResult:
     """lasp_fit_group on device tensors; returns after enqueueing (stream ordered).
     stop_window > 0 turns on the per-spectrum stopping rules (window, stop_tol);
-    polish_iters > 0 adds that many Levenberg-Marquardt iterations at most."""
+    polish_iters > 0 adds that many Levenberg-Marquardt iterations at most;
+    clean_every > 0 turns on the Clean mask updates (every clean_every steps,
+    at most clean_max times)."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
@@ -217,14 +228,18 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
                         if want_cov else None,
                         torch.empty(B, dtype=torch.int32, device=dev),
                         torch.empty(B, dtype=torch.float64, device=dev),
-                        torch.empty(B, dtype=torch.int32, device=dev))
+                        torch.empty(B, dtype=torch.int32, device=dev),
+                        torch.empty((B, P), dtype=torch.uint8, device=dev) if want_mask else None)
     o = make_opts(B, P, margin=margin, degree=degree, precision=precision, lr=lr, betas=betas,
                   eps=eps, weight_quantile=weight_quantile, arms=arms, box=box, stream=stream,
-                  stop_window=stop_window, stop_tol=stop_tol, polish_iters=polish_iters)
+                  stop_window=stop_window, stop_tol=stop_tol, polish_iters=polish_iters,
+                  clean_every=clean_every, clean_max=clean_max)
     o.status = ctypes.c_void_p(out.status.data_ptr())
     o.out_chi2 = ctypes.c_void_p(out.chi2.data_ptr())
     if out.steps is not None:
         o.out_steps = ctypes.c_void_p(out.steps.data_ptr())
+    if out.mask is not None:
+        o.out_mask = ctypes.c_void_p(out.mask.data_ptr())
     with torch.cuda.device(dev):
         rc = lib.lasp_fit_group(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
                                 _ptr(basis), _ptr(init_params), _ptr(out.params), _ptr(out.cov),
@@ -265,6 +280,22 @@ def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False
                               _ptr(res["jac"]), _ptr(res["cov"]), ctypes.byref(o))
     _check(rc)
     return res
+
+
+def clean_mask(obs, ivar, model, wave_grid, f_shift, *, margin=64, stream=None):
+    """lasp_clean_mask: (keep [B, P] uint8, n_masked [B] int32) device tensors."""
+    lib = load()
+    B, P = obs.shape
+    for t, nm in ((obs, "obs"), (ivar, "ivar"), (model, "model")):
+        _dev(t, nm, torch.float32, (B, P))
+    grid = _grid(wave_grid, P)
+    keep = torch.empty((B, P), dtype=torch.uint8, device=obs.device)
+    nm_ = torch.empty(B, dtype=torch.int32, device=obs.device)
+    o = make_opts(B, P, margin=margin, stream=stream)
+    with torch.cuda.device(obs.device):
+        _check(lib.lasp_clean_mask(_ptr(obs), _ptr(ivar), _ptr(model), float(f_shift), _ptr(keep),
+                                   _ptr(nm_), grid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o)))
+    return keep, nm_
 
 
 def release():
