@@ -49,7 +49,13 @@ class _Cfg(ctypes.Structure):
         ("dlog10", ctypes.c_double),
         ("lo", ctypes.c_double * 5),
         ("hi", ctypes.c_double * 5),
+        ("n_classes", ctypes.c_int),
+        ("edges", ctypes.c_double * 4),
     ]
+
+# Teff edges (K) of the emulator's five regimes: cool, cool->warm blend, warm,
+# warm->hot blend, hot.
+REGIME_EDGES = (4000.0, 4550.0, 7000.0, 9000.0)
 
 
 _lib = None
@@ -82,6 +88,11 @@ def _load():
         lib.orc_fit.argtypes = [cp, fp, fp, fp, dp, ctypes.c_int, dp, dp, dp, ip, dp, dp, ip, up]
         lib.orc_fit.restype = ctypes.c_int
         lib.orc_covariance.argtypes = [cp, fp, fp, fp, dp, dp, dp]
+        lib.orc_class_weights.argtypes = [cp, dp, dp, dp]
+        lib.orc_class_weights.restype = None
+        lib.orc_resample.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, fp,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        lib.orc_resample.restype = ctypes.c_int
         lib.orc_stop_rule.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         lib.orc_stop_rule.restype = ctypes.c_int
         lib.orc_stop_step.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ip]
@@ -116,9 +127,14 @@ def _f(a):
 class Config:
     """Grid/shape description for the oracle (plain values, no arithmetic)."""
 
-    def __init__(self, n_pix, margin, degree, dlog10, box_lo, box_hi, arm_start=(), arm_sigma=()):
+    def __init__(self, n_pix, margin, degree, dlog10, box_lo, box_hi, arm_start=(), arm_sigma=(),
+                 n_classes=1, edges=REGIME_EDGES):
         c = _Cfg()
         c.n_pix, c.margin, c.degree = int(n_pix), int(margin), int(degree)
+        c.n_classes = int(n_classes)
+        for i in range(4):
+            c.edges[i] = float(edges[i])
+        self.n_classes = c.n_classes
         c.n_arms = len(arm_start)
         for i, (s, g) in enumerate(zip(arm_start, arm_sigma)):
             c.arm_start[i] = int(s)
@@ -134,9 +150,9 @@ class Config:
         self.box_hi = np.array(box_hi, dtype=np.float64)
 
     @classmethod
-    def from_shape(cls, shape, box_lo, box_hi):
+    def from_shape(cls, shape, box_lo, box_hi, n_classes=1):
         return cls(shape.n_pix, shape.margin, shape.degree, shape.dlog10, box_lo, box_hi,
-                   shape.arm_start, shape.arm_sigma_kms)
+                   shape.arm_start, shape.arm_sigma_kms, n_classes=n_classes)
 
     def normalise(self, phys):
         """Physical (Teff K, logg, [Fe/H], RV, sigma) -> u in the box [-1, 1]."""
@@ -247,6 +263,34 @@ def covariance(cfg: Config, obs, ivar, basis, u):
     rc = lib.orc_covariance(ctypes.byref(cfg.c), _f(obs), _f(ivar), _f(basis), _d(u), _d(cov_u),
                             _d(cov_p))
     return dict(rc=rc, cov_u=cov_u, cov=cov_p)
+
+
+def class_weights(cfg: Config, u):
+    """Emulator class weights at normalised u and their derivatives in u_1."""
+    lib = _load()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    w = np.zeros(3)
+    dw = np.zeros(3)
+    lib.orc_class_weights(ctypes.byref(cfg.c), _d(u), _d(w), _d(dw))
+    return w[:max(cfg.n_classes, 1)], dw[:max(cfg.n_classes, 1)]
+
+
+def resample(src, lam0, dlam, n_out, lg0, dlog10):
+    """Flux-conserving resampling of rows of ``src`` (linear grid, bin
+    centres lam0 + i dlam) onto the log grid 10^(lg0 + j dlog10), j < n_out.
+    Returns (out [rows, n_out] float64, all targets inside the source)."""
+    lib = _load()
+    src = np.atleast_2d(_f32(src))
+    out = np.empty((src.shape[0], n_out))
+    ok = True
+    for r in range(src.shape[0]):
+        row = np.ascontiguousarray(src[r])
+        o = np.empty(n_out)
+        rc = lib.orc_resample(int(row.size), float(lam0), float(dlam), _f(row), int(n_out),
+                              float(lg0), float(dlog10), _d(o))
+        out[r] = o
+        ok = ok and rc == 0
+    return out, ok
 
 
 def stop_step(ell, n_max, window, tol):

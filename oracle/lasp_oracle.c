@@ -62,6 +62,8 @@ typedef struct orc_cfg {
   double arm_sigma[4];
   double dlog10;      /* grid step in log10(lambda) */
   double lo[ORC_NP], hi[ORC_NP];
+  int n_classes;      /* 1, or 3 (cool, warm, hot emulator classes) */
+  double edges[4];    /* Teff regime edges (K) of the 3-class emulator */
 } orc_cfg;
 
 /* Exponents of x1, x2, x3 for each interpolator term: total degree <= 3,
@@ -279,22 +281,57 @@ static void setup_data(const orc_cfg *cfg, const float *obs, const float *ivar, 
   }
 }
 
+/*
+ * Weights of the emulator's temperature classes (Eq. 1 with the five Teff
+ * regimes of the ELODIE emulator): with a = clamp((T - e0) / (e1 - e0)) and
+ * b = clamp((T - e2) / (e3 - e2)), the cool, warm and hot classes weigh
+ * 1 - a, a (1 - b) and a b -- one class inside a regime, a linear blend in
+ * Teff across the two transition regimes.  dw[] is d w / d u_1 (zero where
+ * the blend is flat).  One class: w = 1.
+ */
+void orc_class_weights(const orc_cfg *cfg, const double *u, double *w, double *dw) {
+  if (cfg->n_classes <= 1) {
+    w[0] = 1.0;
+    dw[0] = 0.0;
+    return;
+  }
+  const double lt = cfg->lo[0] + 0.5 * (u[0] + 1.0) * (cfg->hi[0] - cfg->lo[0]);
+  const double T = pow(10.0, lt);
+  const double dT = T * ORC_LN10 * 0.5 * (cfg->hi[0] - cfg->lo[0]);
+  const double *e = cfg->edges;
+  double a = (T - e[0]) / (e[1] - e[0]), da = dT / (e[1] - e[0]);
+  if (!(T > e[0] && T < e[1])) da = 0.0;
+  a = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+  double b = (T - e[2]) / (e[3] - e[2]), db = dT / (e[3] - e[2]);
+  if (!(T > e[2] && T < e[3])) db = 0.0;
+  b = b < 0.0 ? 0.0 : (b > 1.0 ? 1.0 : b);
+  w[0] = 1.0 - a;
+  w[1] = a * (1.0 - b);
+  w[2] = a * b;
+  dw[0] = -da;
+  dw[1] = da * (1.0 - b) - a * db;
+  dw[2] = da * b + a * db;
+}
+
 /* Eq. 1 and Eq. 5 with derivatives: F', F'' and dF''/du at u. */
 static void model_spectrum(const orc_cfg *cfg, const float *basis, const double *u, orc_work *wk,
                            int want_deriv) {
   int P = cfg->n_pix, M = cfg->margin, ne = P + 2 * M;
-  double phi[ORC_NB], dphi[3 * ORC_NB];
+  const int ncl = cfg->n_classes > 1 ? cfg->n_classes : 1;
+  double phi[ORC_NB], dphi[3 * ORC_NB], cw[3], dcw[3];
   orc_features(u, phi, dphi);
+  orc_class_weights(cfg, u, cw, dcw);
   double *dfp = (double *)calloc((size_t)3 * ne, sizeof(double));
   for (int c = 0; c < ne; ++c) {
     double acc = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
-    for (int k = 0; k < ORC_NB; ++k) {
-      double b = basis[(size_t)k * ne + c];
-      acc += phi[k] * b;
-      d0 += dphi[k] * b;
-      d1 += dphi[ORC_NB + k] * b;
-      d2 += dphi[2 * ORC_NB + k] * b;
-    }
+    for (int q = 0; q < ncl; ++q)
+      for (int k = 0; k < ORC_NB; ++k) {
+        double b = basis[((size_t)q * ORC_NB + k) * ne + c];
+        acc += cw[q] * phi[k] * b;
+        d0 += (dcw[q] * phi[k] + cw[q] * dphi[k]) * b;
+        d1 += cw[q] * dphi[ORC_NB + k] * b;
+        d2 += cw[q] * dphi[2 * ORC_NB + k] * b;
+      }
     wk->fp[c] = acc;
     dfp[c] = d0;
     dfp[ne + c] = d1;
@@ -834,4 +871,50 @@ int orc_clean(int n, const float *obs, const float *ivar, const double *model, d
   if (d_iters) *d_iters = it;
   free(valid); free(B); free(C); free(D); free(Dn); free(eps); free(G);
   return masked;
+}
+
+/*
+ * Flux-conserving resampling (Section 2.2, step 3) of one spectrum from a
+ * linear wavelength grid (bin centres lam0 + i dlam, i < n_src) onto a
+ * logarithmic grid of n_out pixels with centres 10^(lg0 + j dlog10), in the
+ * paper's four steps:
+ *   1. integration nodes: the source bin edges lam0 - dlam/2 + k dlam and
+ *      the target edges 10^(lg0 + (j - 1/2) dlog10), j = 0..n_out;
+ *   2. the cumulative integral of the source at its nodes, 0, T_1 dlam,
+ *      (T_1 + T_2) dlam, ...;
+ *   3. that integral interpolated linearly at the target nodes (constant
+ *      beyond the source range);
+ *   4. the differences of step 3 divided by the target bin widths.
+ * Reading: base 10 (the grid of the paper's Section 4), as for the model.
+ * out[j] in FP64.  Returns 0, or -1 if the target range leaves the source.
+ */
+int orc_resample(int n_src, double lam0, double dlam, const float *src, int n_out, double lg0,
+                 double dlog10, double *out) {
+  double *cum = (double *)malloc(sizeof(double) * (size_t)(n_src + 1));
+  cum[0] = 0.0;
+  for (int k = 0; k < n_src; ++k) cum[k + 1] = cum[k] + (double)src[k] * dlam;
+  const double e0 = lam0 - 0.5 * dlam;
+  const double e_end = e0 + n_src * dlam;
+  int rc = 0;
+  double prev_l = 0.0, prev_f = 0.0;
+  for (int j = 0; j <= n_out; ++j) {
+    const double l = pow(10.0, lg0 + ((double)j - 0.5) * dlog10);
+    if (l < e0 || l > e_end) rc = -1;
+    double f;
+    if (l <= e0) {
+      f = 0.0;
+    } else if (l >= e_end) {
+      f = cum[n_src];
+    } else {
+      int k = (int)floor((l - e0) / dlam);
+      if (k > n_src - 1) k = n_src - 1;
+      const double frac = (l - (e0 + k * dlam)) / dlam;
+      f = cum[k] + frac * (cum[k + 1] - cum[k]);
+    }
+    if (j > 0) out[j - 1] = (f - prev_f) / (l - prev_l);
+    prev_l = l;
+    prev_f = f;
+  }
+  free(cum);
+  return rc;
 }

@@ -15,8 +15,11 @@ from .generator import (  # noqa: F401
     BOX_LO,
     C_KMS,
     EXPONENTS,
+    REGIME_EDGES,
     Shape,
     SpectraBatch,
+    class_weights,
+    linear_grid_basis,
     make_basis,
     make_spectra,
     make_spectra_parallel,

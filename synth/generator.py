@@ -155,8 +155,24 @@ def _monomials(x: np.ndarray) -> np.ndarray:
     return np.prod(x[:, None, :] ** e[None, :, :], axis=-1)
 
 
-def _line_list(shape: Shape) -> LineList:
-    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([shape.shape_id, 0xBA515])))
+# Effective-temperature regimes of the multi-class emulator (K): the cool
+# class alone below the first edge, cool -> warm blended linearly in Teff
+# between the first two, warm alone, warm -> hot blended between the last
+# two, hot alone above (the paper's five regimes of the ELODIE emulator).
+REGIME_EDGES = (4000.0, 4550.0, 7000.0, 9000.0)
+
+
+def class_weights(teff: np.ndarray, edges=REGIME_EDGES) -> np.ndarray:
+    """[n] Teff (K) -> [n, 3] weights of the cool, warm and hot classes."""
+    t = np.asarray(teff, dtype=np.float64)
+    a = np.clip((t - edges[0]) / (edges[1] - edges[0]), 0.0, 1.0)   # cool -> warm
+    b = np.clip((t - edges[2]) / (edges[3] - edges[2]), 0.0, 1.0)   # warm -> hot
+    return np.stack([1.0 - a, a * (1.0 - b), a * b], axis=-1)
+
+
+def _line_list(shape: Shape, cls: int = 0) -> LineList:
+    key = [shape.shape_id, 0xBA515] if cls == 0 else [shape.shape_id, 0xBA515, cls]
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(key)))
     ext = _ext_grid(shape)
     centre = rng.uniform(ext[0], ext[-1], N_LINES)
     sigma = rng.uniform(0.5, 3.0, N_LINES)
@@ -169,21 +185,57 @@ def _line_list(shape: Shape) -> LineList:
     return LineList(centre, sigma, coef)
 
 
-def make_basis(shape: Shape) -> tuple[np.ndarray, LineList]:
-    """Interpolator coefficient spectra [20, n_pix + 2*margin] (float32).
+def make_basis(shape: Shape, n_classes: int = 1):
+    """Interpolator coefficient spectra [20 * n_classes, n_pix + 2*margin]
+    (float32) and the line list (a list of n_classes lists when n_classes > 1).
 
-    Row 0 is the line-free unit level minus the constant part of every line's
-    depth; row k > 0 carries monomial k's share of the depths.  Each line
-    profile is averaged over the pixel's wavelength bin (flux conserving).
+    Row 0 of each class is the line-free unit level minus the constant part
+    of every line's depth; row k > 0 carries monomial k's share of the
+    depths.  Each line profile is averaged over the pixel's wavelength bin
+    (flux conserving).  Class c (cool, warm, hot) has its own line depths.
     """
-    lines = _line_list(shape)
     edges = _bin_edges(_ext_grid(shape), shape.dlog10)
-    basis = np.zeros((N_BASIS, shape.n_ext))
-    for k in range(N_BASIS):
-        prof = _binned_gaussians(edges, lines.centre[None, :], lines.sigma[None, :],
-                                 lines.coef[None, :, k])[0]
-        basis[k] = (1.0 if k == 0 else 0.0) - prof
-    return basis.astype(np.float32), lines
+    all_lines = [_line_list(shape, c) for c in range(n_classes)]
+    basis = np.zeros((N_BASIS * n_classes, shape.n_ext))
+    for c, lines in enumerate(all_lines):
+        for k in range(N_BASIS):
+            prof = _binned_gaussians(edges, lines.centre[None, :], lines.sigma[None, :],
+                                     lines.coef[None, :, k])[0]
+            basis[c * N_BASIS + k] = (1.0 if k == 0 else 0.0) - prof
+    return basis.astype(np.float32), (all_lines[0] if n_classes == 1 else all_lines)
+
+
+def linear_grid_basis(shape: Shape, n_classes: int = 1, step: float = 0.2, pad: float = 20.0):
+    """The same coefficient spectra sampled like an emulator's output: on a
+    linear wavelength grid of ``step`` A covering the extended log grid with
+    ``pad`` A to spare, each line averaged over the linear bins.  Returns
+    (lambda0 [A, centre of the first bin], step, [rows, n] float32)."""
+    ext = _ext_grid(shape)
+    lo = ext[0] * 10.0 ** (-0.5 * shape.dlog10) - pad
+    hi = ext[-1] * 10.0 ** (0.5 * shape.dlog10) + pad
+    n = int(math.ceil((hi - lo) / step))
+    centres = lo + step * (np.arange(n) + 0.5)
+    edges = lo + step * np.arange(n + 1)
+    all_lines = [_line_list(shape, c) for c in range(n_classes)]
+    out = np.zeros((N_BASIS * n_classes, n))
+    for c, lines in enumerate(all_lines):
+        for k in range(N_BASIS):
+            prof = _linear_binned_gaussians(edges, lines.centre, lines.sigma, lines.coef[:, k])
+            out[c * N_BASIS + k] = (1.0 if k == 0 else 0.0) - prof
+    return float(centres[0]), float(step), out.astype(np.float32)
+
+
+def _linear_binned_gaussians(edges, centre, sigma, amp):
+    """Sum of amp * (mean of each Gaussian over linear bins ``edges``)."""
+    width = np.diff(edges)
+    out = np.zeros(edges.size - 1)
+    for c, s, a in zip(centre, sigma, amp):
+        i0 = max(0, int(np.searchsorted(edges, c - _WINDOW_SIGMAS * s)) - 1)
+        i1 = min(edges.size - 1, int(np.searchsorted(edges, c + _WINDOW_SIGMAS * s)) + 1)
+        e = edges[i0:i1 + 1]
+        cdf = erf((e - c) / (math.sqrt(2.0) * s))
+        out[i0:i1] += a * s * math.sqrt(math.pi / 2.0) * np.diff(cdf)
+    return out / width
 
 
 def _normalise(theta: np.ndarray) -> np.ndarray:
@@ -231,17 +283,22 @@ def make_spectra(shape: Shape, lines: LineList, config_id: int, start: int, coun
             teff = r.uniform(4000.0, 8000.0)
             th[i] = (math.log10(teff), r.uniform(1.0, 5.0), r.uniform(-2.5, 0.5),
                      r.uniform(-300.0, 300.0), r.uniform(50.0, 150.0))
-        depth = _monomials(_normalise(th)[:, :3]) @ lines.coef.T        # [n, L]
-        dop = np.exp(th[:, 3:4] / C_KMS)                                # [n, 1]
-        cen = lines.centre[None, :] * dop
-        sig_l = lines.sigma[None, :] * dop
-        flux = np.empty((n, P))
-        for a, (j0, j1) in enumerate(zip(arms, arm_end)):
-            s_eff = np.sqrt(th[:, 4:5] ** 2 + arm_sig[a] ** 2)
-            s_tot = np.sqrt(sig_l ** 2 + (cen * s_eff / C_KMS) ** 2)
-            amp = depth * sig_l / s_tot
-            prof = _binned_gaussians(edges[j0:j1 + 1], cen, s_tot, amp)
-            flux[:, j0:j1] = 1.0 - prof
+        classes = lines if isinstance(lines, list) else [lines]
+        cw = class_weights(10.0 ** th[:, 0]) if len(classes) > 1 else np.ones((n, 1))
+        flux = np.zeros((n, P))
+        for ci, cl in enumerate(classes):
+            depth = _monomials(_normalise(th)[:, :3]) @ cl.coef.T     # [n, L]
+            dop = np.exp(th[:, 3:4] / C_KMS)                            # [n, 1]
+            cen = cl.centre[None, :] * dop
+            sig_l = cl.sigma[None, :] * dop
+            fc = np.empty((n, P))
+            for a, (j0, j1) in enumerate(zip(arms, arm_end)):
+                s_eff = np.sqrt(th[:, 4:5] ** 2 + arm_sig[a] ** 2)
+                s_tot = np.sqrt(sig_l ** 2 + (cen * s_eff / C_KMS) ** 2)
+                amp = depth * sig_l / s_tot
+                prof = _binned_gaussians(edges[j0:j1 + 1], cen, s_tot, amp)
+                fc[:, j0:j1] = 1.0 - prof
+            flux += cw[:, ci:ci + 1] * fc
         for i, r in enumerate(rngs):
             s = 10.0 ** r.uniform(1.0, 3.0)
             while True:
