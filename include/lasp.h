@@ -65,13 +65,14 @@ extern "C" {
 #define LASP_PREC_BF16X3 1 /* BF16 hi/lo split contraction, FP32 accumulate */
 
 #define LASP_N_BASIS 20 /* monomials of total degree <= 3 in (u1, u2, u3) */
+#define LASP_MAX_CLASSES 3 /* emulator temperature classes (cool, warm, hot) */
 #define LASP_N_PAR 5
 #define LASP_MAX_ARMS 4
 
 /*
  * Options.  Fill with lasp_default_opts() and override.
  *  n_spec, n_pix   number of spectra B and pixels P per spectrum.
- *  n_basis         must be LASP_N_BASIS; basis row k multiplies monomial k of
+ *  n_basis         must be LASP_N_BASIS * n_classes; basis row k multiplies monomial k of
  *                  (u1, u2, u3) in graded lexicographic order:
  *                  1, u1, u2, u3, u1^2, u1u2, u1u3, u2^2, u2u3, u3^2, u1^3,
  *                  u1^2u2, u1^2u3, u1u2^2, u1u2u3, u1u3^2, u2^3, u2^2u3,
@@ -121,6 +122,16 @@ extern "C" {
  *                  zero weight until the next update.  0 = No Clean.
  *  out_mask        optional device uint8 [n_spec][n_pix]: the last Clean
  *                  mask (1 kept, 0 clipped; all 1 if no update ran).
+ *  n_classes       1, or 3: the interpolator of Eq. 1 over the five Teff
+ *                  regimes of the emulator, with one set of 20 coefficient
+ *                  spectra per temperature class (cool, warm, hot; basis rows
+ *                  20 q .. 20 q + 19 for class q).  At T = 10^(log10 Teff)
+ *                  with a = clamp((T - e0) / (e1 - e0)) and
+ *                  b = clamp((T - e2) / (e3 - e2)) the classes weigh 1 - a,
+ *                  a (1 - b) and a b: one class inside the regimes T <= e0,
+ *                  e1 <= T <= e2 and T >= e3, a linear blend in Teff across
+ *                  (e0, e1) and (e2, e3).  BF16X3 supports one class only.
+ *  class_edges     e0 < e1 < e2 < e3 in K (default 4000, 4550, 7000, 9000).
  */
 typedef struct lasp_opts {
   int32_t n_spec;
@@ -146,6 +157,8 @@ typedef struct lasp_opts {
   int32_t clean_every;
   int32_t clean_max;
   uint8_t *out_mask;
+  int32_t n_classes;
+  double class_edges[4];
 } lasp_opts;
 
 /* Defaults: n_basis 20, margin 64, degree 10, FP32, box
@@ -153,7 +166,8 @@ typedef struct lasp_opts {
  * lr 1e-2, betas (0.9, 0.999), eps 1e-8, weight_quantile 0.5, no arms,
  * null stream, no status/chi2 outputs, stopping rules off (stop_window 0,
  * stop_tol 1e-5), no out_steps, no polish, No Clean (clean_every 0,
- * clean_max 11), no out_mask.  n_spec and n_pix are set to 0. */
+ * clean_max 11), no out_mask, one emulator class (class_edges 4000, 4550,
+ * 7000, 9000 K).  n_spec and n_pix are set to 0. */
 void lasp_default_opts(lasp_opts *opts);
 
 /*
@@ -163,7 +177,7 @@ void lasp_default_opts(lasp_opts *opts);
  *   ivar         [B][P] float   inverse variance; <= 0 or non-finite masks a pixel
  *   wave_grid    HOST [P] double  pixel wavelengths (A); must be uniform in
  *                log10 to 1e-6 of the step, else LASP_E_GRID
- *   basis        [20][P+2M] float interpolator coefficient spectra
+ *   basis        [20 n_classes][P+2M] float interpolator coefficient spectra
  *   init_params  [B][5] float   start, physical units
  *   out_params   [B][5] float   result, physical units (may alias init_params)
  *   out_cov      [B][5][5] double covariance in physical units, or NULL
@@ -214,6 +228,27 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid,
 int lasp_clean_mask(const float *obs, const float *ivar, const float *model, float f_shift,
                     uint8_t *keep, int32_t *n_masked, const double *wave_grid,
                     const lasp_opts *opts);
+
+/*
+ * Flux-conserving resampling (Section 2.2, step 3, Eqs. 2-4) of n_rows
+ * spectra from a linear wavelength grid onto a grid uniform in log10.
+ * Source row r holds the flux of bins centred at lam0 + i dlam (i < n_src,
+ * width dlam); target pixel j of n_out has edges 10^(lg0 + (j -+ 1/2) dlog10).
+ * out[r][j] is the integral of the piecewise-constant source over target
+ * bin j divided by the bin's width: the difference quotient of the
+ * cumulative integral (Eq. 2) interpolated linearly at the edges (Eq. 3),
+ * Eq. 4.  The result is linear in the source and independent of the fitted
+ * parameters, so a basis is resampled once (each of its rows is a spectrum).
+ *   src      device float [n_rows][ld_src], ld_src >= n_src
+ *   out      device float [n_rows][ld_out], ld_out >= n_out (not aliasing src)
+ *   stream   hipStream_t (NULL: the null stream); the call is asynchronous.
+ * The arithmetic is FP64; out is rounded to FP32.  Returns LASP_E_GRID if a
+ * target edge falls outside the source range [lam0 - dlam/2,
+ * lam0 + (n_src - 1/2) dlam], LASP_E_ARG for other invalid arguments.
+ */
+int lasp_resample(const float *src, int32_t n_rows, int32_t n_src, int64_t ld_src, double lam0,
+                  double dlam, float *out, int32_t n_out, int64_t ld_out, double lg0,
+                  double dlog10, void *stream);
 
 /*
  * Kernel timing for benchmarks.  lasp_profile_enable(mask) clears the

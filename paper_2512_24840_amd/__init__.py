@@ -29,4 +29,5 @@ from .lasp import (  # noqa: F401
     profile_enable,
     profile_read,
     release,
+    resample,
 )

@@ -36,6 +36,25 @@ __device__ inline void feature_row(const float *u, int t, float *out) {
   }
 }
 
+// The same row over the three emulator classes: entry 20 q + k is
+// w_q phi_k, and its derivative rows carry d w_q / d u1 phi_k as well.
+__device__ inline void feature_row_classes(const Geometry &g, const float *u, int t, float *out) {
+  const float x = u[0], y = u[1], z = u[2];
+  float phi[kNB], r[kNB], d[3][kNB];
+  features(x, y, z, phi);
+  feature_derivs(x, y, z, d);
+#pragma unroll
+  for (int k = 0; k < kNB; ++k)
+    r[k] = t == 0 ? phi[k] : (t == 1 ? d[0][k] : (t == 2 ? d[1][k] : d[2][k]));
+  float w[kMaxClasses], dw[kMaxClasses];
+  class_weights(g, x, w, dw);
+#pragma unroll
+  for (int q = 0; q < kMaxClasses; ++q)
+#pragma unroll
+    for (int k = 0; k < kNB; ++k)
+      out[kNB * q + k] = t == 1 ? fmaf(dw[q], phi[k], w[q] * r[k]) : w[q] * r[k];
+}
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
 
@@ -169,7 +188,9 @@ __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, in
 }
 
 // F'[r][c] = sum_k Phi[r][k] basis[k][c] for r < rows (rows = B or 4B with
-// derivative rows).  Grid: (ldF / (64 * kFwdTiles), ceil(rows / 16)).
+// derivative rows), k < NB (20, or 60 over three emulator classes).
+// Grid: (ldF / (64 * kFwdTiles), ceil(rows / 16)).
+template <int NB>
 __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int rows_per_spec, int skip_done) {
   __shared__ __align__(16) float sT[16 * kFwdLd];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -186,18 +207,23 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
     if (!any) return;
   }
 
-  float bv[5];
+  float bv[NB / 4];
   {
-    float phi[kNB];
+    float phi[NB];
 #pragma unroll
-    for (int k = 0; k < kNB; ++k) phi[k] = 0.f;
+    for (int k = 0; k < NB; ++k) phi[k] = 0.f;
     if (my_row < rows) {
       const int spec = my_row / rows_per_spec;
       const int t = my_row - spec * rows_per_spec;
-      feature_row(s.u + (size_t)spec * kNP, t, phi);
+      if (NB == kNB)
+        feature_row(s.u + (size_t)spec * kNP, t, phi);
+      else
+        feature_row_classes(g, s.u + (size_t)spec * kNP, t, phi);
     }
+    // selects, not an indexed load: keeps phi in registers
 #pragma unroll
-    for (int kk = 0; kk < 5; ++kk) bv[kk] = phi[4 * kk + kq];
+    for (int kk = 0; kk < NB / 4; ++kk)
+      bv[kk] = kq == 0 ? phi[4 * kk] : (kq == 1 ? phi[4 * kk + 1] : (kq == 2 ? phi[4 * kk + 2] : phi[4 * kk + 3]));
   }
 
   const int cbase = (blockIdx.x * 4 + wave) * (16 * kFwdTiles);
@@ -206,7 +232,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
     if (c0 >= g.ldF) break;
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < 5; ++kk) {
+    for (int kk = 0; kk < NB / 4; ++kk) {
       const float a = s.basis[(size_t)(4 * kk + kq) * g.ldF + c0 + (lane & 15)];
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[kk], acc, 0, 0, 0);
     }
@@ -219,82 +245,98 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
 // Phi-bar[s][k] = sum_c F-bar'[s][c] basis[k][c], then the gradient of
 // J = chi2/n_eff with respect to u and one Adam step (or, with grad_out,
 // the gradient written out and no update).  One workgroup = 16 spectra; its
-// four waves split the columns and combine through LDS.
-template <bool BF16>
+// four waves split the columns and combine through LDS.  Basis rows go in
+// groups of 16 (NG = 2 groups for 20 rows, 4 for 60); rows past NB are zero.
+template <bool BF16, int NB>
 __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg adam,
                                                     int do_adam, float *grad_out) {
-  __shared__ float red[4][16][32];
-  __shared__ float pb[16][kNB];
+  static_assert(!BF16 || NB == kNB, "BF16x3 contraction has one emulator class");
+  constexpr int NG = (NB + 15) / 16;
+  __shared__ float red[4][16][16 * NG];
+  __shared__ float pb[16][NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s0 = blockIdx.x * 16;
   const int i_row = lane & 15;   // spectrum within the tile (A rows) / basis row (B cols)
   const int kq = lane >> 4;
   const bool row_ok = s0 + i_row < g.B;
   const float *fb_row = s.fbar + (size_t)(row_ok ? s0 + i_row : s0) * g.ldF;
-  const bool b1_ok = i_row < kNB - 16;
-  const int b1 = 16 + (b1_ok ? i_row : 0);
+  bool b_ok[NG];
+  int b_row[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    b_ok[q] = 16 * q + i_row < NB;
+    b_row[q] = 16 * q + (b_ok[q] ? i_row : 0);
+  }
   if (s.target) {  // the whole tile finished: nothing to do (uniform over the block)
     bool any = false;
     for (int r = 0; r < 16; ++r) any = any || (s0 + r < g.B && slot_active(s, s0 + r));
     if (!any) return;
   }
 
-  floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  floatx4 acc[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int per_wave = g.ldF / 4;  // ldF is a multiple of 128
   const int cb = wave * per_wave;
   const int ce = cb + per_wave;
-  if (!BF16) {
-    const float *b0_row = s.basis + (size_t)i_row * g.ldF;
-    const float *b1_row = s.basis + (size_t)b1 * g.ldF;
+  if constexpr (!BF16) {
+    const float *b_ptr[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) b_ptr[q] = s.basis + (size_t)b_row[q] * g.ldF;
     // loads of kU column groups are issued before their products (more
-    // bytes in flight); rows past B and basis rows past 19 read a valid row
+    // bytes in flight); rows past B and basis rows past NB read a valid row
     // and are zeroed
-    constexpr int kU = 8;
+    constexpr int kU = NG <= 2 ? 8 : 4;
     int c = cb;
     for (; c + 16 * kU <= ce; c += 16 * kU) {
-      float4 fa[kU], bv0[kU], bv1[kU];
+      float4 fa[kU], bv[kU][NG];
 #pragma unroll
-      for (int q = 0; q < kU; ++q) {
-        const int cc = c + 16 * q + 4 * kq;
-        fa[q] = *reinterpret_cast<const float4 *>(fb_row + cc);
-        bv0[q] = *reinterpret_cast<const float4 *>(b0_row + cc);
-        bv1[q] = *reinterpret_cast<const float4 *>(b1_row + cc);
+      for (int u = 0; u < kU; ++u) {
+        const int cc = c + 16 * u + 4 * kq;
+        fa[u] = *reinterpret_cast<const float4 *>(fb_row + cc);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) bv[u][q] = *reinterpret_cast<const float4 *>(b_ptr[q] + cc);
       }
 #pragma unroll
-      for (int q = 0; q < kU; ++q) {
-        const float4 a = row_ok ? fa[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 b = b1_ok ? bv1[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv0[q].x, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv0[q].y, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv0[q].z, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv0[q].w, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc1, 0, 0, 0);
+      for (int u = 0; u < kU; ++u) {
+        const float4 a = row_ok ? fa[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 b[NG];
+#pragma unroll
+        for (int q = 0; q < NG; ++q) b[q] = b_ok[q] ? bv[u][q] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].x, acc[q], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q].y, acc[q], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[q].z, acc[q], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[q].w, acc[q], 0, 0, 0);
       }
     }
     for (; c < ce; c += 16) {
       const int cc = c + 4 * kq;
       float4 a = *reinterpret_cast<const float4 *>(fb_row + cc);
-      const float4 bv0 = *reinterpret_cast<const float4 *>(b0_row + cc);
-      float4 b = *reinterpret_cast<const float4 *>(b1_row + cc);
       if (!row_ok) a = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (!b1_ok) b = make_float4(0.f, 0.f, 0.f, 0.f);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv0.x, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv0.y, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv0.z, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv0.w, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc1, 0, 0, 0);
+      float4 b[NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        b[q] = *reinterpret_cast<const float4 *>(b_ptr[q] + cc);
+        if (!b_ok[q]) b[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].x, acc[q], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q].y, acc[q], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[q].z, acc[q], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[q].w, acc[q], 0, 0, 0);
     }
   } else {
-    const uint16_t *h0 = s.basis_hi + (size_t)i_row * g.ldF;
-    const uint16_t *l0 = s.basis_lo + (size_t)i_row * g.ldF;
-    const uint16_t *h1 = s.basis_hi + (size_t)b1 * g.ldF;
-    const uint16_t *l1 = s.basis_lo + (size_t)b1 * g.ldF;
+    const uint16_t *h0 = s.basis_hi + (size_t)b_row[0] * g.ldF;
+    const uint16_t *l0 = s.basis_lo + (size_t)b_row[0] * g.ldF;
+    const uint16_t *h1 = s.basis_hi + (size_t)b_row[1] * g.ldF;
+    const uint16_t *l1 = s.basis_lo + (size_t)b_row[1] * g.ldF;
     const bf16x8 zero = __builtin_bit_cast(bf16x8, ushort8{0, 0, 0, 0, 0, 0, 0, 0});
     for (int c = cb; c < ce; c += 32) {
       const int cc = c + 8 * kq;
@@ -313,26 +355,25 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
       const bf16x8 bh0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h0 + cc));
       const bf16x8 bl0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l0 + cc));
       bf16x8 bh1 = zero, bl1 = zero;
-      if (b1_ok) {
+      if (b_ok[1]) {
         bh1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h1 + cc));
         bl1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l1 + cc));
       }
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh1, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl1, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh1, acc1, 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh1, acc[1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl1, acc[1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh1, acc[1], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    red[wave][4 * kq + q][i_row] = acc0[q];
-    red[wave][4 * kq + q][16 + i_row] = acc1[q];
-  }
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) red[wave][4 * kq + q][16 * gi + i_row] = acc[gi][q];
   __syncthreads();
-  for (int e = threadIdx.x; e < 16 * kNB; e += 256) {
-    const int i = e / kNB, k = e - i * kNB;
+  for (int e = threadIdx.x; e < 16 * NB; e += 256) {
+    const int i = e / NB, k = e - i * NB;
     pb[i][k] = ((red[0][i][k] + red[1][i][k]) + red[2][i][k]) + red[3][i][k];
   }
   __syncthreads();
@@ -344,12 +385,36 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
     float d[3][kNB];
     feature_derivs(u[0], u[1], u[2], d);
     float grad[kNP];
+    if constexpr (NB == kNB) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float acc = 0.f;
+      for (int a = 0; a < 3; ++a) {
+        float acc = 0.f;
 #pragma unroll
-      for (int k = 1; k < kNB; ++k) acc = fmaf(pb[t][k], d[a][k], acc);
-      grad[a] = acc;
+        for (int k = 1; k < kNB; ++k) acc = fmaf(pb[t][k], d[a][k], acc);
+        grad[a] = acc;
+      }
+    } else {
+      // d (sum_q w_q phi . Phi-bar_q) / d u_a: the class weights depend on u1
+      float phi[kNB], w[kMaxClasses], dw[kMaxClasses];
+      features(u[0], u[1], u[2], phi);
+      class_weights(g, u[0], w, dw);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) grad[a] = 0.f;
+#pragma unroll
+      for (int q = 0; q < kMaxClasses; ++q) {
+        const float *pq = &pb[t][kNB * q];
+        float sp = 0.f, sd0 = 0.f, sd1 = 0.f, sd2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kNB; ++k) {
+          sp = fmaf(pq[k], phi[k], sp);
+          sd0 = fmaf(pq[k], d[0][k], sd0);
+          sd1 = fmaf(pq[k], d[1][k], sd1);
+          sd2 = fmaf(pq[k], d[2][k], sd2);
+        }
+        grad[0] = fmaf(dw[q], sp, fmaf(w[q], sd0, grad[0]));
+        grad[1] = fmaf(w[q], sd1, grad[1]);
+        grad[2] = fmaf(w[q], sd2, grad[2]);
+      }
     }
     grad[3] = s.g45[(size_t)spec * 2 + 0];
     grad[4] = s.g45[(size_t)spec * 2 + 1];
@@ -417,20 +482,27 @@ hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, 
   const int skip_done = deriv_rows ? 0 : 1;
   if (bf16x3)
     hipLaunchKernelGGL(k_interp_fwd_bf16, grid, dim3(256), 0, st, g, s, rows_per_spec, skip_done);
+  else if (g.nb == kNB)
+    hipLaunchKernelGGL(k_interp_fwd<kNB>, grid, dim3(256), 0, st, g, s, rows_per_spec, skip_done);
   else
-    hipLaunchKernelGGL(k_interp_fwd, grid, dim3(256), 0, st, g, s, rows_per_spec, skip_done);
+    hipLaunchKernelGGL(k_interp_fwd<kNB * kMaxClasses>, grid, dim3(256), 0, st, g, s,
+                       rows_per_spec, skip_done);
   return hipGetLastError();
 }
 
 hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *adam,
                              float *grad_out, int bf16x3, hipStream_t st) {
   AdamCfg a = adam ? *adam : AdamCfg{0.f, 0.f, 0.f, 0.f, 0, 0.f};
+  const dim3 grid((g.B + 15) / 16);
   if (bf16x3)
-    hipLaunchKernelGGL(k_interp_bwd<true>, dim3((g.B + 15) / 16), dim3(256), 0, st, g, s, a,
+    hipLaunchKernelGGL((k_interp_bwd<true, kNB>), grid, dim3(256), 0, st, g, s, a, adam ? 1 : 0,
+                       grad_out);
+  else if (g.nb == kNB)
+    hipLaunchKernelGGL((k_interp_bwd<false, kNB>), grid, dim3(256), 0, st, g, s, a,
                        adam ? 1 : 0, grad_out);
   else
-    hipLaunchKernelGGL(k_interp_bwd<false>, dim3((g.B + 15) / 16), dim3(256), 0, st, g, s, a,
-                       adam ? 1 : 0, grad_out);
+    hipLaunchKernelGGL((k_interp_bwd<false, kNB * kMaxClasses>), grid, dim3(256), 0, st, g, s,
+                       a, adam ? 1 : 0, grad_out);
   return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ struct Workspace {
   int device = 0;
   hipStream_t stream = nullptr;
   size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0, cap_hist = 0, cap_lm = 0;
+  size_t cap_tsplit = 0;  // entries of the transposed BF16 split basis
   size_t cap_model = 0;
   float *model = nullptr;  // [B][P] model for the Clean updates
   State s{};
@@ -76,6 +77,7 @@ void free_ws(Workspace *w) {
   w->s = State{};
   w->lm = lasp::LmState{};
   w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = w->cap_hist = w->cap_lm = 0;
+  w->cap_tsplit = 0;
 }
 
 // Grows the buffers of w to hold g.B spectra of geometry g (fp_rows rows of F'
@@ -90,9 +92,11 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
   const size_t need_ow = B * lasp::kNPL * g.block;
   const size_t need_fp = B * fp_rows * g.ldF;
   const size_t need_fbar = B * g.ldF;
-  const size_t need_basis = (size_t)lasp::kNB * g.ldF;
+  const size_t need_basis = (size_t)g.nb * g.ldF;
+  const size_t need_tsplit = (size_t)32 * g.ldF;
   const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
                       need_fbar > w->cap_fbar || need_basis > w->cap_basis ||
+                      need_tsplit > w->cap_tsplit ||
                       need_hist > w->cap_hist || need_lm > w->cap_lm || !w->s.u;
   if (!regrow) return LASP_OK;
   hipError_t e = hipStreamSynchronize(st);
@@ -135,15 +139,17 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
   if (r == hipSuccess) r = grow(s.fp, w->cap_fp, need_fp);
   if (r == hipSuccess) r = grow(s.fbar, w->cap_fbar, need_fbar);
   if (r == hipSuccess) {
-    size_t cap = w->cap_basis;
+    size_t cap = w->cap_basis, cap2 = w->cap_basis, cap3 = w->cap_basis;
     r = grow(s.basis, cap, need_basis);
-    size_t cap2 = w->cap_basis, cap3 = w->cap_basis;
-    size_t cap4 = w->cap_basis * 32 / lasp::kNB, cap5 = cap4;
     if (r == hipSuccess) r = grow(s.basis_hi, cap2, need_basis);
     if (r == hipSuccess) r = grow(s.basis_lo, cap3, need_basis);
-    if (r == hipSuccess) r = grow(s.basis_thi, cap4, (size_t)32 * g.ldF);
-    if (r == hipSuccess) r = grow(s.basis_tlo, cap5, (size_t)32 * g.ldF);
-    if (r == hipSuccess) w->cap_basis = need_basis;
+    if (r == hipSuccess) w->cap_basis = cap;
+  }
+  if (r == hipSuccess) {
+    size_t cap4 = w->cap_tsplit, cap5 = w->cap_tsplit;
+    r = grow(s.basis_thi, cap4, need_tsplit);
+    if (r == hipSuccess) r = grow(s.basis_tlo, cap5, need_tsplit);
+    if (r == hipSuccess) w->cap_tsplit = cap4;
   }
   if (r != hipSuccess) {
     free_ws(w);
@@ -201,7 +207,18 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
   if (!o) return fail(LASP_E_ARG, "opts is NULL");
   if (o->n_spec < 0) return fail(LASP_E_ARG, "n_spec < 0");
   if (o->n_pix < 32) return fail(LASP_E_ARG, "n_pix must be >= 32");
-  if (o->n_basis != LASP_N_BASIS) return fail(LASP_E_ARG, "n_basis must be 20");
+  if (o->n_classes != 1 && o->n_classes != LASP_MAX_CLASSES)
+    return fail(LASP_E_ARG, "n_classes must be 1 or 3");
+  if (o->n_basis != LASP_N_BASIS * o->n_classes)
+    return fail(LASP_E_ARG, "n_basis must be 20 * n_classes");
+  if (o->n_classes > 1) {
+    for (int i = 0; i < 4; ++i)
+      if (!(o->class_edges[i] > 0.0) || !isfinite(o->class_edges[i]) ||
+          (i > 0 && !(o->class_edges[i] > o->class_edges[i - 1])))
+        return fail(LASP_E_ARG, "class_edges must be positive, finite and increasing");
+    if (o->precision != LASP_PREC_FP32)
+      return fail(LASP_E_UNSUPPORTED, "more than one emulator class needs LASP_PREC_FP32");
+  }
   if (o->margin < 1 || o->margin > 80) return fail(LASP_E_ARG, "margin must be in [1, 80]");
   if (!(o->degree == 4 || o->degree == 6 || o->degree == 8 || o->degree == 10))
     return fail(LASP_E_UNSUPPORTED, "degree must be one of 4, 6, 8, 10");
@@ -279,12 +296,17 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
   g->rv_half = 0.5 * (o->box_hi[3] - o->box_lo[3]);
   g->sg_lo = o->box_lo[4];
   g->sg_half = 0.5 * (o->box_hi[4] - o->box_lo[4]);
+  g->n_classes = o->n_classes;
+  g->nb = lasp::kNB * o->n_classes;
+  g->lt_lo = o->box_lo[0];
+  g->lt_half = 0.5 * (o->box_hi[0] - o->box_lo[0]);
+  for (int i = 0; i < 4; ++i) g->edges[i] = o->class_edges[i];
   if (lasp::fused_smem_bytes(*g) > 160 * 1024)
     return fail(LASP_E_UNSUPPORTED, "shape needs more LDS than a workgroup has");
   return LASP_OK;
 }
 
-// Copies the caller's basis into the zero-padded [20][ldF] layout.
+// Copies the caller's basis into the zero-padded [nb][ldF] layout.
 __global__ void k_copy_basis(const float *src, float *dst, int Pe, int ldF) {
   const int k = blockIdx.y;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ldF; c += gridDim.x * blockDim.x)
@@ -293,7 +315,7 @@ __global__ void k_copy_basis(const float *src, float *dst, int Pe, int ldF) {
 
 int copy_basis(const Geometry &g, const State &s, const float *basis, int bf16x3,
                hipStream_t st) {
-  hipLaunchKernelGGL(k_copy_basis, dim3((g.ldF + 255) / 256, lasp::kNB), dim3(256), 0, st, basis,
+  hipLaunchKernelGGL(k_copy_basis, dim3((g.ldF + 255) / 256, g.nb), dim3(256), 0, st, basis,
                      s.basis, g.Pe, g.ldF);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && bf16x3) e = lasp::launch_split_basis(g, s, st);
@@ -388,6 +410,9 @@ void lasp_default_opts(lasp_opts *o) {
   o->stop_window = 0;
   o->stop_tol = 1e-5f;
   o->clean_max = 11;
+  o->n_classes = 1;
+  const double edges[4] = {4000.0, 4550.0, 7000.0, 9000.0};
+  for (int i = 0; i < 4; ++i) o->class_edges[i] = edges[i];
 }
 
 const char *lasp_last_error(void) { return g_err.c_str(); }
@@ -556,6 +581,35 @@ int lasp_clean_mask(const float *obs, const float *ivar, const float *model, flo
   hipStream_t st = (hipStream_t)opts->stream;
   lasp::CleanArgs ca{obs, ivar, model, f_shift, keep, n_masked, State{}};
   LASP_CHECK(lasp::launch_clean(g, ca, st), "Clean mask");
+  return LASP_OK;
+}
+
+int lasp_resample(const float *src, int32_t n_rows, int32_t n_src, int64_t ld_src, double lam0,
+                  double dlam, float *out, int32_t n_out, int64_t ld_out, double lg0,
+                  double dlog10, void *stream) {
+  g_err.clear();
+  if (n_rows < 0 || n_src < 1 || n_out < 0) return fail(LASP_E_ARG, "need n_rows >= 0, n_src >= 1, n_out >= 0");
+  if (ld_src < n_src || ld_out < n_out) return fail(LASP_E_ARG, "ld_src >= n_src and ld_out >= n_out required");
+  if (!isfinite(lam0) || !(dlam > 0.0) || !isfinite(dlam) || !isfinite(lg0) || !(dlog10 > 0.0) ||
+      !isfinite(dlog10))
+    return fail(LASP_E_ARG, "lam0, lg0 finite and dlam, dlog10 positive and finite required");
+  if (n_rows == 0 || n_out == 0) return LASP_OK;
+  if (!src || !out) return fail(LASP_E_ARG, "src and out are required");
+  const char *s0 = (const char *)src, *s1 = (const char *)(src + (size_t)(n_rows - 1) * ld_src + n_src);
+  const char *o0 = (const char *)out, *o1 = (const char *)(out + (size_t)(n_rows - 1) * ld_out + n_out);
+  if (o0 < s1 && s0 < o1) return fail(LASP_E_ARG, "out must not overlap src");
+  const double e0 = lam0 - 0.5 * dlam, e1 = e0 + (double)n_src * dlam;
+  const double first = pow(10.0, lg0 - 0.5 * dlog10);
+  const double last = pow(10.0, lg0 + ((double)n_out - 0.5) * dlog10);
+  if (!(first >= e0) || !(last <= e1)) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "target edges [%.6f, %.6f] leave the source range [%.6f, %.6f]",
+             first, last, e0, e1);
+    return fail(LASP_E_GRID, buf);
+  }
+  LASP_CHECK(lasp::launch_resample(src, n_rows, n_src, ld_src, lam0, dlam, out, n_out, ld_out,
+                                   lg0, dlog10, (hipStream_t)stream),
+             "resample");
   return LASP_OK;
 }
 

@@ -11,6 +11,7 @@ constexpr double kCkms = 299792.458;            // speed of light, km/s
 constexpr double kLn10 = 2.302585092994045684;  // ln 10
 constexpr float kSigmaFloorPx = 0.1f;           // lower bound of the kernel width, pixels
 constexpr int kNB = 20;                         // interpolator terms (cubic in 3 coordinates)
+constexpr int kMaxClasses = 3;                  // emulator temperature classes
 constexpr int kNP = 5;                          // free parameters per spectrum
 constexpr int kNPL = 17;                        // pixels owned by one lane in the fused pass
 constexpr int kTB = 8;                          // taps per register block
@@ -59,6 +60,10 @@ struct Geometry {
   double inv_scale;             // pixels per km/s = 1 / (c ln10 dlog10)
   double rv_lo, rv_half;        // RV = rv_lo + (u4 + 1) rv_half
   double sg_lo, sg_half;        // sigma = sg_lo + (u5 + 1) sg_half
+  int n_classes;                // 1, or 3 emulator temperature classes
+  int nb;                       // basis rows: kNB * n_classes
+  double lt_lo, lt_half;        // log10 Teff = lt_lo + (u1 + 1) lt_half
+  double edges[4];              // Teff regime edges (K) of the class blend
 };
 
 // Per-spectrum state and scratch owned by the library.
@@ -154,6 +159,9 @@ hipError_t launch_lm_solve(const Geometry &g, const State &s, const LmState &lm,
 hipError_t launch_lm_accept(const Geometry &g, const State &s, const LmState &lm, int last,
                             hipStream_t st);
 hipError_t launch_clean(const Geometry &g, const CleanArgs &a, hipStream_t st);
+hipError_t launch_resample(const float *src, int n_rows, int n_src, int64_t ld_src, double lam0,
+                           double dlam, float *out, int n_out, int64_t ld_out, double lg0,
+                           double dlog10, hipStream_t st);
 bool fused_supported(int block, int nd);
 size_t fused_smem_bytes(const Geometry &g);
 
@@ -169,6 +177,31 @@ __device__ inline void features(float x, float y, float z, float *phi) {
   phi[10] = x * x * x; phi[11] = x * x * y; phi[12] = x * x * z; phi[13] = x * y * y;
   phi[14] = x * y * z; phi[15] = x * z * z; phi[16] = y * y * y; phi[17] = y * y * z;
   phi[18] = y * z * z; phi[19] = z * z * z;
+}
+
+// Weights of the three emulator classes (cool, warm, hot) at u1 (Eq. 1 over
+// the five Teff regimes): with a = clamp((T - e0) / (e1 - e0)) and
+// b = clamp((T - e2) / (e3 - e2)) the weights are 1 - a, a (1 - b) and a b,
+// so one class holds inside a regime and two blend linearly in Teff across a
+// transition regime.  dw = d w / d u1 (zero where the blend is flat).  FP64
+// inside, FP32 out.
+__device__ inline void class_weights(const Geometry &g, float u1, float *w, float *dw) {
+  const double lt = g.lt_lo + ((double)u1 + 1.0) * g.lt_half;
+  const double T = exp(kLn10 * lt);
+  const double dT = T * kLn10 * g.lt_half;
+  const double w01 = g.edges[1] - g.edges[0], w23 = g.edges[3] - g.edges[2];
+  double a = (T - g.edges[0]) / w01, da = dT / w01;
+  if (!(T > g.edges[0] && T < g.edges[1])) da = 0.0;
+  a = fmin(fmax(a, 0.0), 1.0);
+  double b = (T - g.edges[2]) / w23, db = dT / w23;
+  if (!(T > g.edges[2] && T < g.edges[3])) db = 0.0;
+  b = fmin(fmax(b, 0.0), 1.0);
+  w[0] = (float)(1.0 - a);
+  w[1] = (float)(a * (1.0 - b));
+  w[2] = (float)(a * b);
+  dw[0] = (float)(-da);
+  dw[1] = (float)(da * (1.0 - b) - a * db);
+  dw[2] = (float)(da * b + a * db);
 }
 
 // d phi_k / d x_t for t = 0, 1, 2 (d[t][k]).

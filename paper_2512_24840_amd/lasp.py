@@ -37,7 +37,7 @@ N_PAR = 5
 EXPORTED = ("lasp_default_opts", "lasp_fit_group", "lasp_forward", "lasp_last_error",
             "lasp_release", "lasp_profile_enable", "lasp_profile_read", "lasp_pool_slot_bytes",
             "lasp_pool_create", "lasp_pool_load", "lasp_pool_step", "lasp_pool_progress",
-            "lasp_pool_finish", "lasp_pool_destroy", "lasp_clean_mask")
+            "lasp_pool_finish", "lasp_pool_destroy", "lasp_clean_mask", "lasp_resample")
 KERNELS = ("prepare", "interp_fwd", "fused", "interp_bwd", "cov", "finalize")
 
 
@@ -75,6 +75,8 @@ class LaspOpts(ctypes.Structure):
         ("clean_every", ctypes.c_int32),
         ("clean_max", ctypes.c_int32),
         ("out_mask", ctypes.c_void_p),
+        ("n_classes", ctypes.c_int32),
+        ("class_edges", ctypes.c_double * 4),
     ]
 
 
@@ -127,6 +129,10 @@ def load() -> ctypes.CDLL:
         lib.lasp_clean_mask.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, vp,
                                         ctypes.POINTER(LaspOpts)]
         lib.lasp_clean_mask.restype = ctypes.c_int
+        lib.lasp_resample.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_double, vp, ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.c_double, ctypes.c_double, vp]
+        lib.lasp_resample.restype = ctypes.c_int
         lib.lasp_pool_destroy.argtypes = [vp]
         lib.lasp_pool_destroy.restype = ctypes.c_int
         _lib = lib
@@ -163,7 +169,7 @@ class Arms:
 def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
               betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5, arms: Arms | None = None,
               box=None, stream=None, stop_window=0, stop_tol=1e-5, polish_iters=0,
-              clean_every=0, clean_max=11) -> LaspOpts:
+              clean_every=0, clean_max=11, n_classes=1, class_edges=None) -> LaspOpts:
     o = LaspOpts()
     load().lasp_default_opts(ctypes.byref(o))
     o.n_spec, o.n_pix, o.margin, o.degree = int(n_spec), int(n_pix), int(margin), int(degree)
@@ -173,6 +179,11 @@ def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
     o.stop_window, o.stop_tol = int(stop_window), float(stop_tol)
     o.polish_iters = int(polish_iters)
     o.clean_every, o.clean_max = int(clean_every), int(clean_max)
+    o.n_classes = int(n_classes)
+    o.n_basis = N_BASIS * int(n_classes)
+    if class_edges is not None:
+        for i in range(4):
+            o.class_edges[i] = float(class_edges[i])
     if box is not None:
         lo, hi = box
         for t in range(5):
@@ -208,17 +219,19 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
               margin=64, degree=10, precision="fp32", lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
               weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
               stop_window=0, stop_tol=1e-5, polish_iters=0, clean_every=0, clean_max=11,
-              want_mask=False, out: FitResult | None = None) -> FitResult:
+              want_mask=False, n_classes=1, class_edges=None,
+              out: FitResult | None = None) -> FitResult:
     """lasp_fit_group on device tensors; returns after enqueueing (stream ordered).
     stop_window > 0 turns on the per-spectrum stopping rules (window, stop_tol);
     polish_iters > 0 adds that many Levenberg-Marquardt iterations at most;
     clean_every > 0 turns on the Clean mask updates (every clean_every steps,
-    at most clean_max times)."""
+    at most clean_max times); n_classes = 3 takes a [60, P + 2M] basis of
+    three emulator temperature classes blended over the Teff regimes."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
     _dev(ivar, "ivar", torch.float32, (B, P))
-    _dev(basis, "basis", torch.float32, (N_BASIS, P + 2 * margin))
+    _dev(basis, "basis", torch.float32, (N_BASIS * n_classes, P + 2 * margin))
     _dev(init_params, "init_params", torch.float32, (B, N_PAR))
     grid = _grid(wave_grid, P)
     dev = obs.device
@@ -233,7 +246,8 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
     o = make_opts(B, P, margin=margin, degree=degree, precision=precision, lr=lr, betas=betas,
                   eps=eps, weight_quantile=weight_quantile, arms=arms, box=box, stream=stream,
                   stop_window=stop_window, stop_tol=stop_tol, polish_iters=polish_iters,
-                  clean_every=clean_every, clean_max=clean_max)
+                  clean_every=clean_every, clean_max=clean_max, n_classes=n_classes,
+                  class_edges=class_edges)
     o.status = ctypes.c_void_p(out.status.data_ptr())
     o.out_chi2 = ctypes.c_void_p(out.chi2.data_ptr())
     if out.steps is not None:
@@ -250,14 +264,15 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
 
 def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False,
             want_jac=False, want_cov=False, margin=64, degree=10, precision="fp32",
-            weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None) -> dict:
+            weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
+            n_classes=1, class_edges=None) -> dict:
     """lasp_forward: model, chi2, J, n_eff, gradient, model Jacobian and
     covariance at fixed normalised u."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
     _dev(ivar, "ivar", torch.float32, (B, P))
-    _dev(basis, "basis", torch.float32, (N_BASIS, P + 2 * margin))
+    _dev(basis, "basis", torch.float32, (N_BASIS * n_classes, P + 2 * margin))
     _dev(u, "u", torch.float32, (B, N_PAR))
     grid = _grid(wave_grid, P)
     dev = obs.device
@@ -271,7 +286,8 @@ def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False
     res["cov"] = (torch.empty((B, N_PAR, N_PAR), dtype=torch.float64, device=dev)
                   if want_cov else None)
     o = make_opts(B, P, margin=margin, degree=degree, precision=precision,
-                  weight_quantile=weight_quantile, arms=arms, box=box, stream=stream)
+                  weight_quantile=weight_quantile, arms=arms, box=box, stream=stream,
+                  n_classes=n_classes, class_edges=class_edges)
     o.status = ctypes.c_void_p(res["status"].data_ptr())
     with torch.cuda.device(dev):
         rc = lib.lasp_forward(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
@@ -296,6 +312,27 @@ def clean_mask(obs, ivar, model, wave_grid, f_shift, *, margin=64, stream=None):
         _check(lib.lasp_clean_mask(_ptr(obs), _ptr(ivar), _ptr(model), float(f_shift), _ptr(keep),
                                    _ptr(nm_), grid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o)))
     return keep, nm_
+
+
+def resample(src, lam0, dlam, n_out, lg0, dlog10, *, out=None, stream=None):
+    """lasp_resample: rows of src [R, n_src] (float32 device tensor, bin
+    centres lam0 + i dlam) onto n_out log10-uniform pixels centred at
+    10^(lg0 + j dlog10); returns out [R, n_out] float32 (stream ordered)."""
+    lib = load()
+    if src.dim() != 2:
+        raise ValueError("src must be [rows, n_src]")
+    R, n_src = src.shape
+    _dev(src, "src", torch.float32, (R, n_src))
+    if out is None:
+        out = torch.empty((R, int(n_out)), dtype=torch.float32, device=src.device)
+    _dev(out, "out", torch.float32, (R, int(n_out)))
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device)
+    with torch.cuda.device(src.device):
+        _check(lib.lasp_resample(_ptr(src), int(R), int(n_src), int(n_src), float(lam0),
+                                 float(dlam), _ptr(out), int(n_out), int(n_out), float(lg0),
+                                 float(dlog10), ctypes.c_void_p(stream.cuda_stream)))
+    return out
 
 
 def release():
@@ -328,10 +365,11 @@ class Pool:
 
     def __init__(self, wave_grid, basis, capacity, *, margin=64, degree=10, precision="fp32",
                  lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5,
-                 arms: Arms | None = None, box=None, stream=None, stop_window=0, stop_tol=1e-5):
+                 arms: Arms | None = None, box=None, stream=None, stop_window=0, stop_tol=1e-5,
+                 n_classes=1, class_edges=None):
         lib = load()
         P = int(np.asarray(wave_grid).shape[0])
-        _dev(basis, "basis", torch.float32, (N_BASIS, P + 2 * margin))
+        _dev(basis, "basis", torch.float32, (N_BASIS * n_classes, P + 2 * margin))
         self.n_pix, self.capacity = P, int(capacity)
         self.device = basis.device
         self.stream = stream or torch.cuda.Stream(device=self.device)
@@ -339,7 +377,7 @@ class Pool:
         self._opts = make_opts(capacity, P, margin=margin, degree=degree, precision=precision,
                                lr=lr, betas=betas, eps=eps, weight_quantile=weight_quantile,
                                arms=arms, box=box, stream=self.stream, stop_window=stop_window,
-                               stop_tol=stop_tol)
+                               stop_tol=stop_tol, n_classes=n_classes, class_edges=class_edges)
         self.stop_window = int(stop_window)
         self.slot_bytes = int(lib.lasp_pool_slot_bytes(ctypes.byref(self._opts),
                                                        self._grid.ctypes.data_as(ctypes.c_void_p)))

@@ -56,6 +56,7 @@ def test_default_opts():
     assert o.box_hi[3] == 300.0 and o.box_lo[4] == 50.0
     assert o.lr == pytest.approx(1e-2) and o.beta2 == pytest.approx(0.999)
     assert o.weight_quantile == pytest.approx(0.5)
+    assert o.n_classes == 1 and list(o.class_edges) == [4000.0, 4550.0, 7000.0, 9000.0]
 
 
 def _call_fit(o, grid, null_obs=False):
@@ -89,11 +90,41 @@ def _grid(P=64, step=1e-4):
     (dict(n_pix=16), -1),
     (dict(lr=0.0), -1),
     (dict(n_arms=5), -1),
+    (dict(n_classes=2, n_basis=40), -1),
+    (dict(n_classes=3), -1),                      # n_basis must be 60
+    (dict(n_classes=3, n_basis=60, precision=1), -5),
 ])
 def test_invalid_options_rejected_on_host(kw, code):
     o = _opts(**kw)
     assert _call_fit(o, _grid(o.n_pix)) == code
     assert lasp.load().lasp_last_error().decode() != ""
+
+
+def test_class_edges_must_increase():
+    o = _opts(n_classes=3, n_basis=60)
+    o.class_edges[2] = 4000.0
+    assert _call_fit(o, _grid()) == -1
+    assert b"class_edges" in lasp.load().lasp_last_error()
+
+
+def _resample(n_src=100, lam0=4000.0, dlam=0.2, n_out=10, lg0=None, d=1e-5, src=0x1000,
+              out=0x100000):
+    lib = lasp.load()
+    if lg0 is None:
+        lg0 = math.log10(lam0 + 5.0)
+    return lib.lasp_resample(ctypes.c_void_p(src), 3, n_src, n_src, lam0, dlam,
+                             ctypes.c_void_p(out), n_out, n_out, lg0, d, None)
+
+
+def test_resample_validation_on_host():
+    assert _resample(n_src=0) == -1
+    assert _resample(dlam=0.0) == -1
+    assert _resample(d=float("nan")) == -1
+    assert _resample(src=0x1000, out=0x1010) == -1                  # out overlaps src
+    assert b"overlap" in lasp.load().lasp_last_error()
+    assert _resample(lg0=math.log10(3990.0)) == -2                  # starts below the source
+    assert _resample(n_out=1000) == -2                              # runs past its end
+    assert b"leave the source range" in lasp.load().lasp_last_error()
 
 
 def test_nonuniform_grid_rejected():
