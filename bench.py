@@ -66,6 +66,8 @@ def parse(argv=None):
                    help="serving: requests finish when their fits meet the stopping rules")
     p.add_argument("--stop-window", type=int, default=50,
                    help="window of the stopping rules in the early-stop leg")
+    p.add_argument("--emulator-oracle-sample", type=int, default=48,
+                   help="emulator leg: spectra checked against the oracle's 3-class fit")
     p.add_argument("--stop-tol", type=float, default=1e-5,
                    help="loss-change threshold of the stopping rules in the early-stop leg")
     return p.parse_args(argv)
@@ -226,13 +228,20 @@ def main():
         print(json.dumps({"workload": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}))
         return
 
-    from synth import make_basis, make_spectra_parallel, shape_by_name, wave_grid
+    from synth import linear_grid_basis, make_basis, make_spectra_parallel, shape_by_name, wave_grid
 
     shape = shape_by_name("lamost3900")
     B = args.n_spec
+    extra = not args.no_extra_legs
     t_gen = time.time()
     basis, lines = make_basis(shape)
     batch = make_spectra_parallel(shape, lines, 2, 0, B)   # before any GPU use
+    if extra:
+        # three emulator classes over the five Teff regimes, same shape; the
+        # same coefficient spectra on a 0.2 A linear grid for resampling
+        basis3, lines3 = make_basis(shape, n_classes=3)
+        batch3 = make_spectra_parallel(shape, lines3, 3, 0, B)
+        lin_lam0, lin_step, lin_rows = linear_grid_basis(shape, n_classes=3)
     t_gen = time.time() - t_gen
     print(f"[bench] generated {B} spectra x {shape.n_pix} px in {t_gen:.1f}s", file=sys.stderr,
           flush=True)
@@ -281,7 +290,6 @@ def main():
 
     # the same group with the per-spectrum stopping rules of the optimisation
     # stage (window 50, threshold 1e-5 on sqrt(chi2 / n_eff)), timed alone
-    extra = not args.no_extra_legs
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     if extra:
         es_kw = dict(kw, stop_window=args.stop_window, stop_tol=args.stop_tol)
@@ -327,6 +335,61 @@ def main():
             t=t_lm, adam_steps=n_adam, lm_iters=n_lm,
             params=res_lm.params.cpu().numpy().astype(np.float64),
             limit=int(((st_lm & lasp.ST_POLISH_LIMIT) != 0).sum()))
+
+    # emulator legs: the 3-class fit of a 3-class group (500 Adam steps and
+    # the covariance, per-kernel times), and the flux-conserving resampling
+    # of linear-grid rows onto the basis grid for every spectrum of the group
+    # (the per-evaluation resampling of the paper's pipeline, which this
+    # library hoists to one resampling of the basis)
+    if extra:
+        obs3 = torch.from_numpy(batch3.obs).to(dev)
+        ivar3 = torch.from_numpy(batch3.ivar).to(dev)
+        init3 = torch.from_numpy(batch3.init).to(dev)
+        bas3 = torch.from_numpy(basis3).to(dev)
+        kw3 = dict(want_cov=True, margin=shape.margin, degree=shape.degree, n_classes=3)
+        res3 = lasp.fit_group(obs3, ivar3, grid, bas3, init3, args.adam_steps, **kw3)
+        torch.cuda.synchronize()
+        lasp.profile_enable(list(lasp.KERNELS))
+        e0.record(stream)
+        lasp.fit_group(obs3, ivar3, grid, bas3, init3, args.adam_steps, out=res3, **kw3)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_3 = e0.elapsed_time(e1) / 1e3
+        br3 = lasp.profile_read()
+        lasp.profile_enable([])
+        params3 = res3.params.cpu().numpy().astype(np.float64)
+
+        lg0 = np.log10(shape.lam0) - shape.margin * shape.dlog10
+        rows_dev = torch.from_numpy(lin_rows).to(dev)
+        idx = torch.arange(B, device=dev) % lin_rows.shape[0]
+        src = rows_dev.index_select(0, idx).contiguous()          # [B, n_lin]
+        out_rs = lasp.resample(src, lin_lam0, lin_step, shape.n_ext, lg0, shape.dlog10)
+        torch.cuda.synchronize()
+        n_rep = 10
+        e0.record(stream)
+        for _ in range(n_rep):
+            lasp.resample(src, lin_lam0, lin_step, shape.n_ext, lg0, shape.dlog10, out=out_rs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_rs = e0.elapsed_time(e1) / 1e3 / n_rep
+        # algorithmic bytes: the source bins the target range covers, read
+        # once, and the target pixels written once, per row
+        edges = 10.0 ** (lg0 + (np.arange(shape.n_ext + 1) - 0.5) * shape.dlog10)
+        e_src0 = lin_lam0 - 0.5 * lin_step
+        k_first = int(np.floor((edges[0] - e_src0) / lin_step))
+        k_last = int(np.floor((edges[-1] - e_src0) / lin_step))
+        bytes_rs = B * 4.0 * ((k_last - k_first + 1) + shape.n_ext)
+        t_basis = None
+        b_rows = torch.from_numpy(lin_rows).to(dev)
+        lasp.resample(b_rows, lin_lam0, lin_step, shape.n_ext, lg0, shape.dlog10)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n_rep):
+            lasp.resample(b_rows, lin_lam0, lin_step, shape.n_ext, lg0, shape.dlog10)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_basis = e0.elapsed_time(e1) / 1e3 / n_rep
+        del src, out_rs
 
     params = res.params.cpu().numpy().astype(np.float64)
     status = res.status.cpu().numpy()
@@ -388,6 +451,20 @@ def main():
         out[leg] = {"value": B / d["t"], "unit": "spectra/s", "ms_per_group_fit": d["t"] * 1e3,
                     "adam_steps": d["adam_steps"], "max_lm_iters": d["lm_iters"],
                     "hit_iteration_limit": d["limit"]}
+    if extra:
+        out["emulator_3class"] = {
+            "value": B / t_3, "unit": "spectra/s", "ms_per_group_fit": t_3 * 1e3,
+            "classes": 3, "basis_rows": 60, "adam_steps": args.adam_steps,
+            "kernels": {k: {"avg_ms": (ms / n if n else None), "launches_per_fit": n}
+                        for k, (ms, n) in br3.items()}}
+        out["resample"] = {
+            "value": B / t_rs, "unit": "rows/s", "ms_per_launch": t_rs * 1e3,
+            "rows": B, "n_src": int(lin_rows.shape[1]), "n_out": shape.n_ext,
+            "roofline": {"bound": "hbm", "achieved": bytes_rs / t_rs / 1e9,
+                         "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": bytes_rs / t_rs / PEAK_HBM, "traffic": None,
+                         "bytes_per_launch": bytes_rs},
+            "basis_60_rows_ms": t_basis * 1e3}
 
     if not args.no_cpu_baseline:
         import oracle
@@ -424,6 +501,30 @@ def main():
                 "max_abs_err": {k: float(v) for k, v in zip(("teff_K", "logg", "feh", "rv_kms"),
                                                             e.max(axis=0))}}
         if extra:
+            n3 = min(args.emulator_oracle_sample, B)
+            cfg3 = oracle.Config.from_shape(shape, BOX_LO, BOX_HI, n_classes=3)
+            t = time.perf_counter()
+            ref3 = oracle.fit_many(cfg3, batch3.obs[:n3], batch3.ivar[:n3], basis3,
+                                   batch3.init[:n3], threads=threads)
+            dt3 = time.perf_counter() - t
+            refp3 = np.array([r["params"] for r in ref3])
+            e3 = np.abs(params3[:n3] - refp3)[:, :4]
+            # fits that end at a regime edge (kink of the class blend) are
+            # compared by chi2, as in the parity tests
+            edges = np.array([4000.0, 4550.0, 7000.0, 9000.0])
+            kink = np.min(np.abs(refp3[:, :1] - edges[None, :]), axis=1) < 30.0
+            ok3 = np.all(e3 <= FIT_TOL, axis=1)
+            for i in np.where(kink & ~ok3)[0]:
+                c = oracle.evaluate(cfg3, batch3.obs[i], batch3.ivar[i], basis3,
+                                    cfg3.normalise(params3[i]))["chi2"]
+                ok3[i] = c <= ref3[i]["chi2"] + 0.1
+            out["emulator_3class"]["oracle_match"] = {
+                "n": n3, "matched": int(ok3.sum()), "at_regime_edge": int(kink.sum()),
+                "oracle_spectra_per_s": n3 / dt3,
+                "max_abs_err_away_from_edges": {
+                    k: float(v) for k, v in zip(("teff_K", "logg", "feh", "rv_kms"),
+                                                e3[~kink].max(axis=0) if (~kink).any()
+                                                else np.zeros(4))}}
             err_es = np.abs(params_es[:n] - refp)[:, :4]
             out["early_stop"]["oracle_match"] = {
                 "n": n, "matched": int(np.all(err_es <= FIT_TOL, axis=1).sum()),
