@@ -242,16 +242,107 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
   fwd_store(g, s, sT, r0, rows);
 }
 
-// Phi-bar[s][k] = sum_c F-bar'[s][c] basis[k][c], then the gradient of
-// J = chi2/n_eff with respect to u and one Adam step (or, with grad_out,
-// the gradient written out and no update).  One workgroup = 16 spectra; its
-// four waves split the columns and combine through LDS.  Basis rows go in
-// groups of 16 (NG = 2 groups for 20 rows, 4 for 60); rows past NB are zero.
-template <bool BF16, int NB>
-__global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg adam,
-                                                    int do_adam, float *grad_out) {
-  static_assert(!BF16 || NB == kNB, "BF16x3 contraction has one emulator class");
-  constexpr int NG = (NB + 15) / 16;
+// Gradient of J with respect to u from Phi-bar (pb, NB entries) and the
+// fused pass's dJ/du4, dJ/du5, then the stopping rules and one Adam step of
+// spectrum spec (or the gradient written out).
+template <int NB>
+__device__ inline void bwd_epilogue(const Geometry &g, const State &s, const AdamCfg &adam,
+                                    int do_adam, float *grad_out, int spec, const float *pb) {
+  float *u = s.u + (size_t)spec * kNP;
+  float d[3][kNB];
+  feature_derivs(u[0], u[1], u[2], d);
+  float grad[kNP];
+  if constexpr (NB == kNB) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 1; k < kNB; ++k) acc = fmaf(pb[k], d[a][k], acc);
+      grad[a] = acc;
+    }
+  } else {
+    // d (sum_q w_q phi . Phi-bar_q) / d u_a: the class weights depend on u1
+    float phi[kNB], w[kMaxClasses], dw[kMaxClasses];
+    features(u[0], u[1], u[2], phi);
+    class_weights(g, u[0], w, dw);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) grad[a] = 0.f;
+#pragma unroll
+    for (int q = 0; q < kMaxClasses; ++q) {
+      const float *pq = &pb[kNB * q];
+      float sp = 0.f, sd0 = 0.f, sd1 = 0.f, sd2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < kNB; ++k) {
+        sp = fmaf(pq[k], phi[k], sp);
+        sd0 = fmaf(pq[k], d[0][k], sd0);
+        sd1 = fmaf(pq[k], d[1][k], sd1);
+        sd2 = fmaf(pq[k], d[2][k], sd2);
+      }
+      grad[0] = fmaf(dw[q], sp, fmaf(w[q], sd0, grad[0]));
+      grad[1] = fmaf(w[q], sd1, grad[1]);
+      grad[2] = fmaf(w[q], sd2, grad[2]);
+    }
+  }
+  grad[3] = s.g45[(size_t)spec * 2 + 0];
+  grad[4] = s.g45[(size_t)spec * 2 + 1];
+  if (grad_out) {
+#pragma unroll
+    for (int a = 0; a < kNP; ++a) grad_out[(size_t)spec * kNP + a] = grad[a];
+  }
+  bool take = do_adam && slot_active(s, spec);
+  if (take && adam.stop_window > 0) {
+    // stopping rules of stage 8 on ell_t = sqrt(chi2 / n_eff) after t steps:
+    // a change below stop_tol over the last W steps, or a rise at each of
+    // them (the ring holds ell of the last W step counts)
+    const int t0 = s.t[spec], W = adam.stop_window;
+    const int n = s.neff[spec];
+    const double ell = n > 0 ? sqrt(s.chi2[spec] / (double)n) : 0.0;
+    double *h = s.lhist + (size_t)spec * W;
+    int rise = s.nrise[spec];
+    if (t0 >= 1) rise = ell > h[(t0 - 1) % W] ? rise + 1 : 0;
+    uint32_t bit = 0;
+    if (t0 >= W && fabs(h[t0 % W] - ell) < (double)adam.stop_tol)
+      bit = kStStopFlat;
+    else if (rise >= W)
+      bit = kStStopRising;
+    s.nrise[spec] = rise;
+    h[t0 % W] = ell;
+    if (bit) {
+      s.target[spec] = t0;
+      s.status[spec] |= bit;
+      take = false;
+    }
+  }
+  if (take) {
+    const int step = s.t[spec] + 1;
+    s.t[spec] = step;
+    if (adam.stop_window > 0 && step >= s.target[spec]) s.status[spec] |= kStNotConverged;
+    const float bc1 = 1.f - powf(adam.beta1, (float)step);
+    const float bc2 = 1.f - powf(adam.beta2, (float)step);
+    const float step_size = adam.lr / bc1;
+    const float rbc2 = 1.f / sqrtf(bc2);
+    float *m = s.m + (size_t)spec * kNP;
+    float *v = s.v + (size_t)spec * kNP;
+#pragma unroll
+    for (int a = 0; a < kNP; ++a) {
+      const float ga = grad[a];
+      const float ma = adam.beta1 * m[a] + (1.f - adam.beta1) * ga;
+      const float va = adam.beta2 * v[a] + (1.f - adam.beta2) * ga * ga;
+      m[a] = ma;
+      v[a] = va;
+      const float denom = sqrtf(va) * rbc2 + adam.eps;
+      u[a] = u[a] - step_size * (ma / denom);
+    }
+  }
+}
+
+// BF16x3 variant of the adjoint contraction (one emulator class): one
+// workgroup = 16 spectra; its four waves split the columns and combine
+// through LDS.
+__global__ __launch_bounds__(256) void k_interp_bwd_bf16(Geometry g, State s, AdamCfg adam,
+                                                         int do_adam, float *grad_out) {
+  constexpr int NB = kNB;
+  constexpr int NG = 2;
   __shared__ float red[4][16][16 * NG];
   __shared__ float pb[16][NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -279,93 +370,38 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
   const int per_wave = g.ldF / 4;  // ldF is a multiple of 128
   const int cb = wave * per_wave;
   const int ce = cb + per_wave;
-  if constexpr (!BF16) {
-    const float *b_ptr[NG];
+  const uint16_t *h0 = s.basis_hi + (size_t)b_row[0] * g.ldF;
+  const uint16_t *l0 = s.basis_lo + (size_t)b_row[0] * g.ldF;
+  const uint16_t *h1 = s.basis_hi + (size_t)b_row[1] * g.ldF;
+  const uint16_t *l1 = s.basis_lo + (size_t)b_row[1] * g.ldF;
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, ushort8{0, 0, 0, 0, 0, 0, 0, 0});
+  for (int c = cb; c < ce; c += 32) {
+    const int cc = c + 8 * kq;
+    float fa[8];
+    if (row_ok) {
+      const float4 x0 = *reinterpret_cast<const float4 *>(fb_row + cc);
+      const float4 x1 = *reinterpret_cast<const float4 *>(fb_row + cc + 4);
+      fa[0] = x0.x; fa[1] = x0.y; fa[2] = x0.z; fa[3] = x0.w;
+      fa[4] = x1.x; fa[5] = x1.y; fa[6] = x1.z; fa[7] = x1.w;
+    } else {
 #pragma unroll
-    for (int q = 0; q < NG; ++q) b_ptr[q] = s.basis + (size_t)b_row[q] * g.ldF;
-    // loads of kU column groups are issued before their products (more
-    // bytes in flight); rows past B and basis rows past NB read a valid row
-    // and are zeroed
-    constexpr int kU = NG <= 2 ? 8 : 4;
-    int c = cb;
-    for (; c + 16 * kU <= ce; c += 16 * kU) {
-      float4 fa[kU], bv[kU][NG];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int cc = c + 16 * u + 4 * kq;
-        fa[u] = *reinterpret_cast<const float4 *>(fb_row + cc);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) bv[u][q] = *reinterpret_cast<const float4 *>(b_ptr[q] + cc);
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const float4 a = row_ok ? fa[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float4 b[NG];
-#pragma unroll
-        for (int q = 0; q < NG; ++q) b[q] = b_ok[q] ? bv[u][q] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].x, acc[q], 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q].y, acc[q], 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[q].z, acc[q], 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[q].w, acc[q], 0, 0, 0);
-      }
+      for (int e = 0; e < 8; ++e) fa[e] = 0.f;
     }
-    for (; c < ce; c += 16) {
-      const int cc = c + 4 * kq;
-      float4 a = *reinterpret_cast<const float4 *>(fb_row + cc);
-      if (!row_ok) a = make_float4(0.f, 0.f, 0.f, 0.f);
-      float4 b[NG];
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        b[q] = *reinterpret_cast<const float4 *>(b_ptr[q] + cc);
-        if (!b_ok[q]) b[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-#pragma unroll
-      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q].x, acc[q], 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q].y, acc[q], 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[q].z, acc[q], 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[q].w, acc[q], 0, 0, 0);
+    bf16x8 a_hi, a_lo;
+    split8(fa, a_hi, a_lo);
+    const bf16x8 bh0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h0 + cc));
+    const bf16x8 bl0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l0 + cc));
+    bf16x8 bh1 = zero, bl1 = zero;
+    if (b_ok[1]) {
+      bh1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h1 + cc));
+      bl1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l1 + cc));
     }
-  } else {
-    const uint16_t *h0 = s.basis_hi + (size_t)b_row[0] * g.ldF;
-    const uint16_t *l0 = s.basis_lo + (size_t)b_row[0] * g.ldF;
-    const uint16_t *h1 = s.basis_hi + (size_t)b_row[1] * g.ldF;
-    const uint16_t *l1 = s.basis_lo + (size_t)b_row[1] * g.ldF;
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, ushort8{0, 0, 0, 0, 0, 0, 0, 0});
-    for (int c = cb; c < ce; c += 32) {
-      const int cc = c + 8 * kq;
-      float fa[8];
-      if (row_ok) {
-        const float4 x0 = *reinterpret_cast<const float4 *>(fb_row + cc);
-        const float4 x1 = *reinterpret_cast<const float4 *>(fb_row + cc + 4);
-        fa[0] = x0.x; fa[1] = x0.y; fa[2] = x0.z; fa[3] = x0.w;
-        fa[4] = x1.x; fa[5] = x1.y; fa[6] = x1.z; fa[7] = x1.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) fa[e] = 0.f;
-      }
-      bf16x8 a_hi, a_lo;
-      split8(fa, a_hi, a_lo);
-      const bf16x8 bh0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h0 + cc));
-      const bf16x8 bl0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l0 + cc));
-      bf16x8 bh1 = zero, bl1 = zero;
-      if (b_ok[1]) {
-        bh1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(h1 + cc));
-        bl1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(l1 + cc));
-      }
-      acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh0, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh1, acc[1], 0, 0, 0);
-      acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl0, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl1, acc[1], 0, 0, 0);
-      acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh0, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh1, acc[1], 0, 0, 0);
-    }
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh0, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, bh1, acc[1], 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl0, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bl1, acc[1], 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh0, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, bh1, acc[1], 0, 0, 0);
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q)
@@ -379,95 +415,116 @@ __global__ __launch_bounds__(256) void k_interp_bwd(Geometry g, State s, AdamCfg
   __syncthreads();
 
   const int t = threadIdx.x;
-  if (t < 16 && s0 + t < g.B) {
-    const int spec = s0 + t;
-    float *u = s.u + (size_t)spec * kNP;
-    float d[3][kNB];
-    feature_derivs(u[0], u[1], u[2], d);
-    float grad[kNP];
-    if constexpr (NB == kNB) {
+  if (t < 16 && s0 + t < g.B) bwd_epilogue<NB>(g, s, adam, do_adam, grad_out, s0 + t, pb[t]);
+}
+
+// Phi-bar[s][k] = sum_c F-bar'[s][c] basis[k][c], then the gradient of
+// J = chi2/n_eff with respect to u and one Adam step (or, with grad_out,
+// the gradient written out and no update).  One workgroup = 32 spectra in
+// two 16-row tiles; each of its eight waves covers ldF / 8 columns for both
+// tiles, so one basis load feeds both, and the waves combine through LDS in
+// a fixed order.  Basis rows go in groups of 16 (NG = 2 groups for 20 rows,
+// 4 for 60); the loads of rows past NB are skipped and count as zero.
+template <int NB>
+__global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg adam,
+                                                      int do_adam, float *grad_out) {
+  constexpr int NG = (NB + 15) / 16;
+  constexpr int NWV = 8;
+  __shared__ float red[NWV][32][16 * NG];
+  __shared__ float pb[32][NB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s0 = blockIdx.x * 32;
+  const int i_row = lane & 15;
+  const int kq = lane >> 4;
+  bool row_ok[2];
+  const float *fb_row[2];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 1; k < kNB; ++k) acc = fmaf(pb[t][k], d[a][k], acc);
-        grad[a] = acc;
-      }
-    } else {
-      // d (sum_q w_q phi . Phi-bar_q) / d u_a: the class weights depend on u1
-      float phi[kNB], w[kMaxClasses], dw[kMaxClasses];
-      features(u[0], u[1], u[2], phi);
-      class_weights(g, u[0], w, dw);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) grad[a] = 0.f;
-#pragma unroll
-      for (int q = 0; q < kMaxClasses; ++q) {
-        const float *pq = &pb[t][kNB * q];
-        float sp = 0.f, sd0 = 0.f, sd1 = 0.f, sd2 = 0.f;
-#pragma unroll
-        for (int k = 0; k < kNB; ++k) {
-          sp = fmaf(pq[k], phi[k], sp);
-          sd0 = fmaf(pq[k], d[0][k], sd0);
-          sd1 = fmaf(pq[k], d[1][k], sd1);
-          sd2 = fmaf(pq[k], d[2][k], sd2);
-        }
-        grad[0] = fmaf(dw[q], sp, fmaf(w[q], sd0, grad[0]));
-        grad[1] = fmaf(w[q], sd1, grad[1]);
-        grad[2] = fmaf(w[q], sd2, grad[2]);
-      }
-    }
-    grad[3] = s.g45[(size_t)spec * 2 + 0];
-    grad[4] = s.g45[(size_t)spec * 2 + 1];
-    if (grad_out) {
-#pragma unroll
-      for (int a = 0; a < kNP; ++a) grad_out[(size_t)spec * kNP + a] = grad[a];
-    }
-    bool take = do_adam && slot_active(s, spec);
-    if (take && adam.stop_window > 0) {
-      // stopping rules of stage 8 on ell_t = sqrt(chi2 / n_eff) after t steps:
-      // a change below stop_tol over the last W steps, or a rise at each of
-      // them (the ring holds ell of the last W step counts)
-      const int t0 = s.t[spec], W = adam.stop_window;
-      const int n = s.neff[spec];
-      const double ell = n > 0 ? sqrt(s.chi2[spec] / (double)n) : 0.0;
-      double *h = s.lhist + (size_t)spec * W;
-      int rise = s.nrise[spec];
-      if (t0 >= 1) rise = ell > h[(t0 - 1) % W] ? rise + 1 : 0;
-      uint32_t bit = 0;
-      if (t0 >= W && fabs(h[t0 % W] - ell) < (double)adam.stop_tol)
-        bit = kStStopFlat;
-      else if (rise >= W)
-        bit = kStStopRising;
-      s.nrise[spec] = rise;
-      h[t0 % W] = ell;
-      if (bit) {
-        s.target[spec] = t0;
-        s.status[spec] |= bit;
-        take = false;
-      }
-    }
-    if (take) {
-      const int step = s.t[spec] + 1;
-      s.t[spec] = step;
-      if (adam.stop_window > 0 && step >= s.target[spec]) s.status[spec] |= kStNotConverged;
-      const float bc1 = 1.f - powf(adam.beta1, (float)step);
-      const float bc2 = 1.f - powf(adam.beta2, (float)step);
-      const float step_size = adam.lr / bc1;
-      const float rbc2 = 1.f / sqrtf(bc2);
-      float *m = s.m + (size_t)spec * kNP;
-      float *v = s.v + (size_t)spec * kNP;
-#pragma unroll
-      for (int a = 0; a < kNP; ++a) {
-        const float ga = grad[a];
-        const float ma = adam.beta1 * m[a] + (1.f - adam.beta1) * ga;
-        const float va = adam.beta2 * v[a] + (1.f - adam.beta2) * ga * ga;
-        m[a] = ma;
-        v[a] = va;
-        const float denom = sqrtf(va) * rbc2 + adam.eps;
-        u[a] = u[a] - step_size * (ma / denom);
-      }
-    }
+  for (int rt = 0; rt < 2; ++rt) {
+    row_ok[rt] = s0 + 16 * rt + i_row < g.B;
+    fb_row[rt] = s.fbar + (size_t)(row_ok[rt] ? s0 + 16 * rt + i_row : s0) * g.ldF;
   }
+  bool b_ok[NG];
+  const float *b_ptr[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    b_ok[q] = 16 * q + i_row < NB;
+    b_ptr[q] = s.basis + (size_t)(16 * q + (b_ok[q] ? i_row : 0)) * g.ldF;
+  }
+  if (s.target) {
+    bool any = false;
+    for (int r = 0; r < 32; ++r) any = any || (s0 + r < g.B && slot_active(s, s0 + r));
+    if (!any) return;
+  }
+  floatx4 acc[2][NG];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int q = 0; q < NG; ++q) acc[rt][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int per_wave = g.ldF / NWV;  // ldF is a multiple of 128
+  const int cb = wave * per_wave, ce = cb + per_wave;
+  constexpr int kU = 4;
+  auto step = [&](const float4 (&fa)[2], const float4 (&bv)[NG]) {
+    float4 a[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) a[rt] = row_ok[rt] ? fa[rt] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].x, bv[q].x, acc[rt][q], 0, 0, 0);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].y, bv[q].y, acc[rt][q], 0, 0, 0);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].z, bv[q].z, acc[rt][q], 0, 0, 0);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].w, bv[q].w, acc[rt][q], 0, 0, 0);
+  };
+  auto load = [&](int cc, float4 (&fa)[2], float4 (&bv)[NG]) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) fa[rt] = *reinterpret_cast<const float4 *>(fb_row[rt] + cc);
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      if (16 * q + 16 <= NB || b_ok[q])
+        bv[q] = *reinterpret_cast<const float4 *>(b_ptr[q] + cc);
+      else
+        bv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  int c = cb;
+  for (; c + 16 * kU <= ce; c += 16 * kU) {
+    float4 fa[kU][2], bv[kU][NG];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) load(c + 16 * u + 4 * kq, fa[u], bv[u]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) step(fa[u], bv[u]);
+  }
+  for (; c < ce; c += 16) {
+    float4 fa[2], bv[NG];
+    load(c + 4 * kq, fa, bv);
+    step(fa, bv);
+  }
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) red[wave][16 * rt + 4 * kq + r][16 * q + i_row] = acc[rt][q][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * NB; e += 512) {
+    const int i = e / NB, k = e - i * NB;
+    float v = red[0][i][k];
+#pragma unroll
+    for (int w = 1; w < NWV; ++w) v += red[w][i][k];
+    pb[i][k] = v;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 32 && s0 + t < g.B) bwd_epilogue<NB>(g, s, adam, do_adam, grad_out, s0 + t, pb[t]);
 }
 
 }  // namespace
@@ -495,14 +552,13 @@ hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *a
   AdamCfg a = adam ? *adam : AdamCfg{0.f, 0.f, 0.f, 0.f, 0, 0.f};
   const dim3 grid((g.B + 15) / 16);
   if (bf16x3)
-    hipLaunchKernelGGL((k_interp_bwd<true, kNB>), grid, dim3(256), 0, st, g, s, a, adam ? 1 : 0,
-                       grad_out);
+    hipLaunchKernelGGL(k_interp_bwd_bf16, grid, dim3(256), 0, st, g, s, a, adam ? 1 : 0, grad_out);
   else if (g.nb == kNB)
-    hipLaunchKernelGGL((k_interp_bwd<false, kNB>), grid, dim3(256), 0, st, g, s, a,
+    hipLaunchKernelGGL((k_interp_bwd<kNB>), dim3((g.B + 31) / 32), dim3(512), 0, st, g, s, a,
                        adam ? 1 : 0, grad_out);
   else
-    hipLaunchKernelGGL((k_interp_bwd<false, kNB * kMaxClasses>), grid, dim3(256), 0, st, g, s,
-                       a, adam ? 1 : 0, grad_out);
+    hipLaunchKernelGGL((k_interp_bwd<kNB * kMaxClasses>), dim3((g.B + 31) / 32), dim3(512), 0,
+                       st, g, s, a, adam ? 1 : 0, grad_out);
   return hipGetLastError();
 }
 
