@@ -1,8 +1,9 @@
 // Fused per-spectrum pass of one Adam step (Section 2.2, stages 4-8):
 //   Eq. 5  Gaussian kernel G(mu, sigma) and F'' = F' (x) G, F' staged in LDS
 //   Eq. 6  continuum by weighted least squares: moments of W F''^2 and
-//          W F'' o against Chebyshev polynomials, normal equations solved
-//          in FP64 (Gauss-Jordan, one lane per row)
+//          W F'' o against Chebyshev polynomials (per-lane FP32 sums over 17
+//          pixels, FP64 across lanes), normal equations solved in FP64
+//          (Gauss-Jordan, one lane per row)
 //   Eq. 7  residual e = o - C F'';  Eq. 9 chi2 = sum W e^2 (per spectrum)
 //   adjoint of J = chi2 / n_eff with the continuum at its least-squares
 //          value (envelope theorem): g_j = -2 W e C / n_eff, the lag
@@ -205,38 +206,41 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     }
   }
 
-  // ---- Eq. 6 moments in FP64: nu_l = sum W F''^2 T_l, r_n = sum W F'' o T_n
-  //      (two passes over the pixels: fewer accumulators live at once)
+  // ---- Eq. 6 moments: nu_l = sum W F''^2 T_l, r_n = sum W F'' o T_n.  Each
+  //      lane sums its 17 pixels in FP32; the sums over lanes and waves, and
+  //      the solve, are FP64.  Two passes (nu, then r): fewer live values.
   {
-    const double two_over_p = 2.0 / (double)P;
     double *scr = reinterpret_cast<double *>(sF + L.gb_off);
+    const float two_over_p = 2.f / (float)P;
     {
 #pragma unroll
       for (int i = 0; i < kNPL; ++i) {
         opaque(fpp[i]);
         opaque(ow[i]);
       }
-      double acc[NNU];
+      float nu[NNU];
 #pragma unroll
-      for (int k = 0; k < NNU; ++k) acc[k] = 0.0;
+      for (int k = 0; k < NNU; ++k) nu[k] = 0.f;
 #pragma unroll
       for (int i = 0; i < kNPL; ++i) {
-        const double x = fma((double)(j0 + i), two_over_p, -1.0);
-        const double f = (double)fpp[i];
-        const double y = (double)ow[i].y * f * f;
-        double tm = 1.0, tc = x;
-        acc[0] += y;
-        acc[1] = fma(y, x, acc[1]);
-        const double x2 = x + x;
+        const float x = fmaf((float)(j0 + i), two_over_p, -1.f);
+        const float y = ow[i].y * fpp[i] * fpp[i];
+        float tm = 1.f, tc = x;
+        nu[0] += y;
+        nu[1] = fmaf(y, x, nu[1]);
+        const float x2 = x + x;
 #pragma unroll
         for (int l = 2; l < NNU; ++l) {
-          const double tn = fma(x2, tc, -tm);
-          acc[l] = fma(y, tn, acc[l]);
+          const float tn = fmaf(x2, tc, -tm);
+          nu[l] = fmaf(y, tn, nu[l]);
           tm = tc;
           tc = tn;
         }
         __builtin_amdgcn_sched_barrier(0);
       }
+      double acc[NNU];
+#pragma unroll
+      for (int k = 0; k < NNU; ++k) acc[k] = (double)nu[k];
       block_sum_lds<NW, NNU>(acc, scr, sRed, sMom, lane, wave);
     }
     {
@@ -247,26 +251,29 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       }
       int jb = j0;
       opaque(jb);
-      double acc[ND];
+      float rr[ND];
 #pragma unroll
-      for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+      for (int k = 0; k < ND; ++k) rr[k] = 0.f;
 #pragma unroll
       for (int i = 0; i < kNPL; ++i) {
-        const double x = fma((double)(jb + i), two_over_p, -1.0);
-        const double z = (double)ow[i].y * (double)fpp[i] * (double)ow[i].x;
-        double tm = 1.0, tc = x;
-        acc[0] += z;
-        acc[1] = fma(z, x, acc[1]);
-        const double x2 = x + x;
+        const float x = fmaf((float)(jb + i), two_over_p, -1.f);
+        const float z = ow[i].y * fpp[i] * ow[i].x;
+        float tm = 1.f, tc = x;
+        rr[0] += z;
+        rr[1] = fmaf(z, x, rr[1]);
+        const float x2 = x + x;
 #pragma unroll
         for (int l = 2; l < ND; ++l) {
-          const double tn = fma(x2, tc, -tm);
-          acc[l] = fma(z, tn, acc[l]);
+          const float tn = fmaf(x2, tc, -tm);
+          rr[l] = fmaf(z, tn, rr[l]);
           tm = tc;
           tc = tn;
         }
         __builtin_amdgcn_sched_barrier(0);
       }
+      double acc[ND];
+#pragma unroll
+      for (int k = 0; k < ND; ++k) acc[k] = (double)rr[k];
       block_sum_lds<NW, ND>(acc, scr, sRed, sMom + NNU, lane, wave);
     }
     for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
@@ -316,7 +323,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   const float inv_neff = n_eff > 0 ? 1.f / (float)n_eff : 0.f;
   const float wsc = s.wscale[spec];
   float gb[kNPL];
-  double chi2_part = 0.0;
+  float chi2_part = 0.f;  // this lane's 17 terms; lanes and waves add in FP64
   float cmin = INFINITY;
   {
     float c[ND];
@@ -339,7 +346,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       const float mdl = C * fpp[i];
       const float e = ow[i].x - mdl;
       const float we = ow[i].y * e;
-      chi2_part = fma((double)we, (double)e, chi2_part);
+      chi2_part = fmaf(we, e, chi2_part);
       gb[i] = ok ? -2.f * we * C * inv_neff : 0.f;
       cmin = fminf(cmin, j < P ? C : INFINITY);
       if (j < P) {
@@ -349,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     }
   }
   {
-    const double cs = wave_sum(chi2_part);
+    const double cs = wave_sum((double)chi2_part);
     const float cm = wave_min(cmin);
     if (lane == 0) {
       sRed[wave * 64 + 0] = cs;
