@@ -399,6 +399,22 @@ def main():
         t_basis = e0.elapsed_time(e1) / 1e3 / n_rep
         del src, out_rs
 
+    # throughput against the group size N (the paper's group-size study): the
+    # first N spectra of the same workload, 500 steps + covariance, timed alone
+    sweep = []
+    for n_g in ((1, 10, 100, 1000, 2500, 10000, B) if extra else ()):
+        n_g = min(n_g, B)
+        sl = slice(0, n_g)
+        o_g, iv_g, in_g = obs[sl].contiguous(), ivar[sl].contiguous(), init[sl].contiguous()
+        r_g = lasp.fit_group(o_g, iv_g, grid, bas, in_g, args.adam_steps, **kw)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        lasp.fit_group(o_g, iv_g, grid, bas, in_g, args.adam_steps, out=r_g, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_g = e0.elapsed_time(e1) / 1e3
+        sweep.append({"n": n_g, "spectra_per_s": n_g / t_g, "ms_per_group_fit": t_g * 1e3})
+
     # mixed precision: the same group with both contractions in BF16x3, and a
     # served stream (continuous batching, both shapes) in BF16x3
     if extra:
@@ -508,6 +524,7 @@ def main():
                     "adam_steps": d["adam_steps"], "max_lm_iters": d["lm_iters"],
                     "hit_iteration_limit": d["limit"]}
     if extra:
+        out["n_sweep"] = sweep
         out["bf16x3"] = {"value": B / t_b, "unit": "spectra/s", "ms_per_group_fit": t_b * 1e3,
                          "dtype": "bf16x3",
                          "note": "both interpolator contractions on BF16 matrix cores with "
