@@ -219,7 +219,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         sys.stderr.write("bench.py measures one MI355X only: the grouped fit needs no "
-                         "communication and this build runs no multi-GPU path.\n")
+                         "communication and the library runs no multi-GPU path.\n")
         sys.exit(2)
     if args.workload == "serving":
         return main_serving(args)

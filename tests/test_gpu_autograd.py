@@ -110,8 +110,8 @@ def test_covariance_at_given_u_matches_oracle():
         assert np.linalg.norm(cov[i] - ref) <= 1e-3 * np.linalg.norm(ref), i
 
 
-def test_config4_fullsize_adjoint_and_covariance_on_sample():
-    print("[config 4] 65536 x 3900: gradient + covariance at fixed u, 64 sampled", flush=True)
+def test_adjoint_and_covariance_65536x3900_on_sample():
+    print("[adjoint + covariance] 65536 x 3900: gradient + covariance at fixed u, 64 sampled", flush=True)
     shape = shape_by_name("lamost3900")
     basis, lines = make_basis(shape)
     B = 65536

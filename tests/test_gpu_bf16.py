@@ -44,8 +44,8 @@ def test_bf16x3_forward_errors_vs_oracle():
     assert max(m_err) < 5e-5 and max(c_err) < 1e-3 and max(g_err) < 1e-3
 
 
-def test_config3_bf16x3_grouped_fit_errors_on_sample():
-    print("[config 3] bf16x3, 262144 spectra (16384 distinct x 16), 500 steps, 256 sampled",
+def test_bf16x3_grouped_fit_262144x3900_errors_on_sample():
+    print("[bf16x3 grouped fit] 262144 spectra (16384 distinct x 16), 500 steps, 256 sampled",
           flush=True)
     shape = shape_by_name("lamost3900")
     basis, lines = make_basis(shape)

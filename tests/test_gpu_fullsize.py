@@ -16,7 +16,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 FIT_TOL = np.array([2.0, 0.005, 0.005, 0.2])
 
 
-def test_config2_grouped_fit_matches_oracle_on_sample():
+def test_grouped_fit_16384x3900_matches_oracle_on_sample():
     print("[full size] lamost3900 B=16384, 500 steps, covariance; oracle on 256", flush=True)
     shape = shape_by_name("lamost3900")
     basis, lines = make_basis(shape)
