@@ -45,6 +45,8 @@ FWD_CASES = [
     ("desi7800", {}),
     ("lamost3900", dict(n_pix=1001, margin=40, degree=6)),
     ("lamost3900", dict(n_pix=257, margin=17, degree=4)),
+    # one arm over 7,800 px: the 512-thread workgroup of the one-arm pass
+    ("desi7800", dict(arm_start=(), arm_sigma_kms=())),
 ]
 
 
