@@ -101,6 +101,12 @@ extern "C" {
  *                  (LASP_ST_NOT_CONVERGED).  W = stop_window <= 4096; the
  *                  paper's window is 50 and its threshold 1e-5.  A stopped
  *                  fit takes no further steps; the others are not affected.
+ *                  With the rules on, lasp_fit_group lists the fits still
+ *                  stepping every 16 steps so that the step kernels cover
+ *                  only those, and waits on its stream (for the list length
+ *                  of 16 steps earlier) so that it stops enqueuing steps
+ *                  once every fit has stopped: the call then returns about
+ *                  16 steps before the stream finishes instead of at once.
  *  out_steps       optional device int32 [n_spec]: Adam steps each fit took.
  *  polish_iters    after the Adam steps, up to this many Levenberg-Marquardt
  *                  iterations per spectrum (0 = none): damped Gauss-Newton

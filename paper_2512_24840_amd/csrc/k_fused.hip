@@ -84,8 +84,9 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   int *sHa = reinterpret_cast<int *>(sScal + 16);      // [kMaxArms]
   double *sSp = sScal + 24;                            // [kMaxArms]
 
-  const int spec = blockIdx.x;
-  if (ADJ && !slot_active(s, spec)) return;  // finished slot of a pool: no step
+  if ((int)blockIdx.x >= work_count(g, s)) return;  // past the active list
+  const int spec = work_spec(s, blockIdx.x);
+  if (ADJ && !slot_active(s, spec)) return;  // finished slot: no step
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int P = g.P, M = g.M;
   const int j0 = tid * kNPL;           // first pixel (and basis column) of this lane

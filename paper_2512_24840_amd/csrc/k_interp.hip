@@ -111,8 +111,15 @@ __device__ inline void fwd_stage(float *sT, int wave, int lane, int n, const flo
       make_float4(v[0], v[1], v[2], v[3]);
 }
 
+// Row r of the launch (entry r / rps of the work list, derivative row
+// r % rps) lands in F' row spec * rps + r % rps.
+__device__ inline int fwd_dst_row(const State &s, int r, int rps) {
+  const int e = r / rps;
+  return work_spec(s, e) * rps + (r - e * rps);
+}
+
 __device__ inline void fwd_store(const Geometry &g, const State &s, const float *sT, int r0,
-                                 int rows) {
+                                 int rows, int rps) {
   const int c_base = blockIdx.x * kFwdCols;
 #pragma unroll
   for (int q = 0; q < 16 * kFwdCols / 4 / 256; ++q) {
@@ -120,7 +127,7 @@ __device__ inline void fwd_store(const Geometry &g, const State &s, const float 
     const int r = e / (kFwdCols / 4), c4 = e - r * (kFwdCols / 4);
     const int col = c_base + 4 * c4;
     if (r0 + r < rows && col < g.ldF)
-      *reinterpret_cast<float4 *>(s.fp + (size_t)(r0 + r) * g.ldF + col) =
+      *reinterpret_cast<float4 *>(s.fp + (size_t)fwd_dst_row(s, r0 + r, rps) * g.ldF + col) =
           *reinterpret_cast<const float4 *>(sT + r * kFwdLd + 4 * c4);
   }
 }
@@ -129,15 +136,16 @@ __device__ inline void fwd_store(const Geometry &g, const State &s, const float 
 __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, int rows_per_spec, int skip_done) {
   __shared__ __align__(16) float sT[16 * kFwdLd];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rows = g.B * rows_per_spec;
+  const int rows = work_count(g, s) * rows_per_spec;
   const int r0 = blockIdx.y * 16;
+  if (r0 >= rows) return;  // past the work list (uniform over the block)
   const int my_row = r0 + (lane & 15);
   const int kq = lane >> 4;
   if (skip_done && s.target) {
     bool any = false;
     for (int r = 0; r < 16; ++r) {
       const int row = r0 + r;
-      any = any || (row < rows && slot_active(s, row / rows_per_spec));
+      any = any || (row < rows && slot_active(s, work_spec(s, row / rows_per_spec)));
     }
     if (!any) return;
   }
@@ -148,9 +156,9 @@ __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, in
 #pragma unroll
     for (int k = 0; k < 32; ++k) phi[k] = 0.f;
     if (my_row < rows) {
-      const int spec = my_row / rows_per_spec;
-      const int t = my_row - spec * rows_per_spec;
-      feature_row(s.u + (size_t)spec * kNP, t, phi);
+      const int e = my_row / rows_per_spec;
+      const int t = my_row - e * rows_per_spec;
+      feature_row(s.u + (size_t)work_spec(s, e) * kNP, t, phi);
     }
     phi0 = phi[0];
     phi[0] = 0.f;  // constant row added in FP32 below
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, in
     fwd_stage(sT, wave, lane, n, out);
   }
   __syncthreads();
-  fwd_store(g, s, sT, r0, rows);
+  fwd_store(g, s, sT, r0, rows, rows_per_spec);
 }
 
 // F'[r][c] = sum_k Phi[r][k] basis[k][c] for r < rows (rows = B or 4B with
@@ -194,15 +202,16 @@ template <int NB>
 __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int rows_per_spec, int skip_done) {
   __shared__ __align__(16) float sT[16 * kFwdLd];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rows = g.B * rows_per_spec;
+  const int rows = work_count(g, s) * rows_per_spec;
   const int r0 = blockIdx.y * 16;
+  if (r0 >= rows) return;  // past the work list (uniform over the block)
   const int my_row = r0 + (lane & 15);
   const int kq = lane >> 4;  // k offset inside a group of 4
   if (skip_done && s.target) {
     bool any = false;
     for (int r = 0; r < 16; ++r) {
       const int row = r0 + r;
-      any = any || (row < rows && slot_active(s, row / rows_per_spec));
+      any = any || (row < rows && slot_active(s, work_spec(s, row / rows_per_spec)));
     }
     if (!any) return;
   }
@@ -213,12 +222,13 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
 #pragma unroll
     for (int k = 0; k < NB; ++k) phi[k] = 0.f;
     if (my_row < rows) {
-      const int spec = my_row / rows_per_spec;
-      const int t = my_row - spec * rows_per_spec;
+      const int e = my_row / rows_per_spec;
+      const int t = my_row - e * rows_per_spec;
+      const float *ur = s.u + (size_t)work_spec(s, e) * kNP;
       if (NB == kNB)
-        feature_row(s.u + (size_t)spec * kNP, t, phi);
+        feature_row(ur, t, phi);
       else
-        feature_row_classes(g, s.u + (size_t)spec * kNP, t, phi);
+        feature_row_classes(g, ur, t, phi);
     }
     // selects, not an indexed load: keeps phi in registers
 #pragma unroll
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
     fwd_stage(sT, wave, lane, n, acc);
   }
   __syncthreads();
-  fwd_store(g, s, sT, r0, rows);
+  fwd_store(g, s, sT, r0, rows, rows_per_spec);
 }
 
 // Gradient of J with respect to u from Phi-bar (pb, NB entries) and the
@@ -347,10 +357,12 @@ __global__ __launch_bounds__(256) void k_interp_bwd_bf16(Geometry g, State s, Ad
   __shared__ float pb[16][NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s0 = blockIdx.x * 16;
+  const int count = work_count(g, s);
+  if (s0 >= count) return;  // past the work list (uniform over the block)
   const int i_row = lane & 15;   // spectrum within the tile (A rows) / basis row (B cols)
   const int kq = lane >> 4;
-  const bool row_ok = s0 + i_row < g.B;
-  const float *fb_row = s.fbar + (size_t)(row_ok ? s0 + i_row : s0) * g.ldF;
+  const bool row_ok = s0 + i_row < count;
+  const float *fb_row = s.fbar + (size_t)work_spec(s, row_ok ? s0 + i_row : s0) * g.ldF;
   bool b_ok[NG];
   int b_row[NG];
 #pragma unroll
@@ -360,7 +372,7 @@ __global__ __launch_bounds__(256) void k_interp_bwd_bf16(Geometry g, State s, Ad
   }
   if (s.target) {  // the whole tile finished: nothing to do (uniform over the block)
     bool any = false;
-    for (int r = 0; r < 16; ++r) any = any || (s0 + r < g.B && slot_active(s, s0 + r));
+    for (int r = 0; r < 16; ++r) any = any || (s0 + r < count && slot_active(s, work_spec(s, s0 + r)));
     if (!any) return;
   }
 
@@ -415,7 +427,8 @@ __global__ __launch_bounds__(256) void k_interp_bwd_bf16(Geometry g, State s, Ad
   __syncthreads();
 
   const int t = threadIdx.x;
-  if (t < 16 && s0 + t < g.B) bwd_epilogue<NB>(g, s, adam, do_adam, grad_out, s0 + t, pb[t]);
+  if (t < 16 && s0 + t < count)
+    bwd_epilogue<NB>(g, s, adam, do_adam, grad_out, work_spec(s, s0 + t), pb[t]);
 }
 
 // Phi-bar[s][k] = sum_c F-bar'[s][c] basis[k][c], then the gradient of
@@ -434,14 +447,16 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
   __shared__ float pb[32][NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s0 = blockIdx.x * 32;
+  const int count = work_count(g, s);
+  if (s0 >= count) return;  // past the work list (uniform over the block)
   const int i_row = lane & 15;
   const int kq = lane >> 4;
   bool row_ok[2];
   const float *fb_row[2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt) {
-    row_ok[rt] = s0 + 16 * rt + i_row < g.B;
-    fb_row[rt] = s.fbar + (size_t)(row_ok[rt] ? s0 + 16 * rt + i_row : s0) * g.ldF;
+    row_ok[rt] = s0 + 16 * rt + i_row < count;
+    fb_row[rt] = s.fbar + (size_t)work_spec(s, row_ok[rt] ? s0 + 16 * rt + i_row : s0) * g.ldF;
   }
   bool b_ok[NG];
   const float *b_ptr[NG];
@@ -452,7 +467,7 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
   }
   if (s.target) {
     bool any = false;
-    for (int r = 0; r < 32; ++r) any = any || (s0 + r < g.B && slot_active(s, s0 + r));
+    for (int r = 0; r < 32; ++r) any = any || (s0 + r < count && slot_active(s, work_spec(s, s0 + r)));
     if (!any) return;
   }
   floatx4 acc[2][NG];
@@ -524,7 +539,8 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
   }
   __syncthreads();
   const int t = threadIdx.x;
-  if (t < 32 && s0 + t < g.B) bwd_epilogue<NB>(g, s, adam, do_adam, grad_out, s0 + t, pb[t]);
+  if (t < 32 && s0 + t < count)
+    bwd_epilogue<NB>(g, s, adam, do_adam, grad_out, work_spec(s, s0 + t), pb[t]);
 }
 
 }  // namespace

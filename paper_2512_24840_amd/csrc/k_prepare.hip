@@ -179,6 +179,32 @@ __global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double
 }
 
 // Steps taken and stopped flag of each slot.
+// The spectra still taking steps, in index order: each thread counts the
+// active spectra of its contiguous chunk, a workgroup-wide scan of the
+// counts gives each chunk's first position, and each thread writes its
+// chunk.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_compact(Geometry g, State s, int *order,
+                                                  int *n_active) {
+  __shared__ int cnt[1024];
+  const int t = threadIdx.x;
+  const int chunk = (g.B + 1023) / 1024;
+  const int b0 = min(t * chunk, g.B), b1 = min(b0 + chunk, g.B);
+  int c = 0;
+  for (int i = b0; i < b1; ++i) c += slot_active(s, i) ? 1 : 0;
+  cnt[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+    const int v = t >= off ? cnt[t - off] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  int pos = cnt[t] - c;
+  for (int i = b0; i < b1; ++i)
+    if (slot_active(s, i)) order[pos++] = i;
+  if (t == 1023) *n_active = cnt[1023];
+}
+
 __global__ void k_progress(Geometry g, State s, int32_t *steps, int32_t *done) {
   const int spec = blockIdx.x * blockDim.x + threadIdx.x;
   if (spec >= g.B) return;
@@ -228,6 +254,12 @@ hipError_t launch_finalize(const Geometry &g, const State &s, const double *lo, 
   hipLaunchKernelGGL(k_finalize, dim3((g.B + bs - 1) / bs), dim3(bs), 0, st, g, s, lo[0], lo[1],
                      lo[2], lo[3], lo[4], hi[0], hi[1], hi[2], hi[3], hi[4], out_params,
                      status_out, chi2_out, steps_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const Geometry &g, const State &s, int *order, int *n_active,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, g, s, order, n_active);
   return hipGetLastError();
 }
 

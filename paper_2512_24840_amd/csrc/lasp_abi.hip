@@ -36,6 +36,10 @@ struct Workspace {
   hipStream_t stream = nullptr;
   size_t cap_B = 0, cap_ow = 0, cap_fp = 0, cap_fbar = 0, cap_basis = 0, cap_hist = 0, cap_lm = 0;
   size_t cap_tsplit = 0;  // entries of the transposed BF16 split basis
+  size_t cap_order = 0;
+  int *order = nullptr;     // [B] active list of the stopping rules, then its length
+  int *h_active = nullptr;  // pinned [2]: lengths read back by the host
+  hipEvent_t ev[2] = {nullptr, nullptr};
   size_t cap_model = 0;
   float *model = nullptr;  // [B][P] model for the Clean updates
   State s{};
@@ -74,6 +78,15 @@ void free_ws(Workspace *w) {
   if (w->model) (void)hipFree(w->model);
   w->model = nullptr;
   w->cap_model = 0;
+  if (w->order) (void)hipFree(w->order);
+  w->order = nullptr;
+  w->cap_order = 0;
+  if (w->h_active) (void)hipHostFree(w->h_active);
+  w->h_active = nullptr;
+  for (hipEvent_t &e : w->ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   w->s = State{};
   w->lm = lasp::LmState{};
   w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = w->cap_hist = w->cap_lm = 0;
@@ -94,9 +107,10 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
   const size_t need_fbar = B * g.ldF;
   const size_t need_basis = (size_t)g.nb * g.ldF;
   const size_t need_tsplit = (size_t)32 * g.ldF;
+  const size_t need_order = hist_w > 0 ? B + 1 : 0;
   const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
                       need_fbar > w->cap_fbar || need_basis > w->cap_basis ||
-                      need_tsplit > w->cap_tsplit ||
+                      need_tsplit > w->cap_tsplit || need_order > w->cap_order ||
                       need_hist > w->cap_hist || need_lm > w->cap_lm || !w->s.u;
   if (!regrow) return LASP_OK;
   hipError_t e = hipStreamSynchronize(st);
@@ -121,6 +135,7 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
     if (r == hipSuccess) w->cap_B = B;
   }
   if (r == hipSuccess && need_hist > 0) r = grow(s.lhist, w->cap_hist, need_hist);
+  if (r == hipSuccess && need_order > 0) r = grow(w->order, w->cap_order, need_order);
   if (r == hipSuccess && need_lm > w->cap_lm) {
     lasp::LmState &l = w->lm;
     const size_t cl = w->cap_lm;
@@ -379,6 +394,9 @@ void prof_drain() {
 
 #define LASP_TIMED(cls, st) ProfScope prof_scope_##__LINE__((cls), (st))
 
+// Steps between two compactions of the active list (stopping rules on).
+constexpr int kCompactEvery = 16;
+
 #define LASP_CHECK(call, what)                 \
   do {                                         \
     hipError_t e_ = (call);                    \
@@ -503,15 +521,46 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   }
   const lasp::AdamCfg adam{opts->lr, opts->beta1, opts->beta2, opts->eps, W, opts->stop_tol};
   s.fp_stride = g.ldF;
+  if (W > 0 && !w->h_active) {
+    hipError_t e = hipHostMalloc((void **)&w->h_active, 2 * sizeof(int));
+    for (int k = 0; e == hipSuccess && k < 2; ++k)
+      e = hipEventCreateWithFlags(&w->ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) return dev_fail(e, "active-list events");
+  }
   for (int it = 0; it < n_steps; ++it) {
+    if (W > 0 && it > 0 && it % kCompactEvery == 0) {
+      // the spectra still stepping, listed so that the per-step kernels cover
+      // those only (a fit's arithmetic does not depend on its place)
+      State all = s;
+      all.order = nullptr;
+      LASP_CHECK(lasp::launch_compact(g, all, w->order, w->order + g.B, st), "active list");
+      s.order = w->order;
+      s.n_active = w->order + g.B;
+      // once no fit is active, stop enqueuing steps: the host reads the list
+      // length of the previous compaction, whose steps the device is still
+      // working through, so the wait leaves no gap
+      const int slot = (it / kCompactEvery) & 1;
+      LASP_CHECK(hipMemcpyAsync(w->h_active + slot, w->order + g.B, sizeof(int),
+                                hipMemcpyDeviceToHost, st),
+                 "active count");
+      LASP_CHECK(hipEventRecord(w->ev[slot], st), "active count event");
+      if (it >= 2 * kCompactEvery) {
+        LASP_CHECK(hipEventSynchronize(w->ev[slot ^ 1]), "active count wait");
+        if (w->h_active[slot ^ 1] == 0) break;
+      }
+    }
     {
       LASP_TIMED(LASP_K_INTERP_FWD, st);
       LASP_CHECK(lasp::launch_interp_fwd(g, s, 0, bf16, st), "interpolator contraction");
     }
     if (ce > 0 && it > 0 && it % ce == 0 && it / ce <= cm) {
       // Clean update: residual of the current model, new mask and weights
-      LASP_CHECK(lasp::launch_fused(g, s, 0, w->model, st), "fused pass (model)");
-      lasp::CleanArgs ca{obs, ivar, w->model, it == ce ? 0.5f : 0.2f, opts->out_mask, nullptr, s};
+      // (every spectrum, as without the active list)
+      State sc = s;
+      sc.order = nullptr;
+      sc.n_active = nullptr;
+      LASP_CHECK(lasp::launch_fused(g, sc, 0, w->model, st), "fused pass (model)");
+      lasp::CleanArgs ca{obs, ivar, w->model, it == ce ? 0.5f : 0.2f, opts->out_mask, nullptr, sc};
       LASP_CHECK(lasp::launch_clean(g, ca, st), "Clean mask");
     }
     {
@@ -526,6 +575,8 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   // chi2 and status at the returned parameters (every spectrum, stopped or
   // not); derivative rows for the covariance
   s.target = nullptr;
+  s.order = nullptr;
+  s.n_active = nullptr;
   if (polish > 0) {
     // Levenberg-Marquardt polish from the Adam end point
     const lasp::LmState lm = w->lm;

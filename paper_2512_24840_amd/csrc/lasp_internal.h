@@ -84,7 +84,12 @@ struct State {
   double *chi2;     // [B]
   double *lhist;    // [B][stop window] loss history ring (stopping rules)
   int *nrise;       // [B] consecutive steps at which the loss rose
-  float *basis;     // [20][ldF] zero-padded copy of the basis
+  // Optional list of the spectra still taking steps (stopping rules on):
+  // the per-step kernels then work on order[0 .. *n_active) instead of
+  // 0 .. B.  NULL: every spectrum, in index order.
+  const int *order;     // [B] spectrum indices, active ones first
+  const int *n_active;  // [1] length of the list
+  float *basis;     // [nb][ldF] zero-padded copy of the basis
   uint16_t *basis_hi;  // [20][ldF] bf16 high part (BF16x3, adjoint contraction)
   uint16_t *basis_lo;  // [20][ldF] bf16 low part
   uint16_t *basis_thi; // [ldF][32] bf16 high part, k-major per column, rows 1..19 (forward)
@@ -133,7 +138,16 @@ hipError_t launch_prepare(const Geometry &g, const State &s, const float *obs, c
 __device__ inline bool slot_active(const State &s, int spec) {
   return s.target == nullptr || s.t[spec] < s.target[spec];
 }
+// Entries the per-step kernels cover, and the spectrum of entry i.
+__device__ inline int work_count(const Geometry &g, const State &s) {
+  return s.order ? *s.n_active : g.B;
+}
+__device__ inline int work_spec(const State &s, int i) { return s.order ? s.order[i] : i; }
 #endif
+// Writes the spectra with slot_active true, in index order, to order and
+// their number to n_active (one workgroup).
+hipError_t launch_compact(const Geometry &g, const State &s, int *order, int *n_active,
+                          hipStream_t st);
 hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, int bf16x3,
                              hipStream_t st);
 hipError_t launch_fused(const Geometry &g, const State &s, int adjoint, float *model_out,
