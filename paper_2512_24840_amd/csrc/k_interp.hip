@@ -443,8 +443,13 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
                                                       int do_adam, float *grad_out) {
   constexpr int NG = (NB + 15) / 16;
   constexpr int NWV = 8;
-  __shared__ float red[NWV][32][16 * NG];
+  constexpr int kSLd = 68;                        // staging row stride (floats)
+  constexpr int kStage = 32 * kSLd;               // one wave's [32 rows][64 columns]
+  constexpr int kRed = 32 * 16 * NG;              // one wave's partial sums
+  constexpr int kBuf = NWV * (kStage > kRed ? kStage : kRed);
+  __shared__ __align__(16) float sbuf[kBuf];      // staging, then the partial sums
   __shared__ float pb[32][NB];
+  auto red = reinterpret_cast<float (*)[32][16 * NG]>(sbuf);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s0 = blockIdx.x * 32;
   const int count = work_count(g, s);
@@ -510,19 +515,53 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
         bv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
+  // F-bar' goes through this wave's LDS stage, 32 rows x 64 columns at a
+  // time, read with row-contiguous loads (256-byte runs per row); the MFMA
+  // operands (16 rows x 4 columns per lane group) come from LDS
+  float *stg = sbuf + wave * kStage;
+  const float *rp[8];
+  bool rv[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int ri = 4 * j + (lane >> 4);
+    rv[j] = s0 + ri < count;
+    rp[j] = s.fbar + (size_t)work_spec(s, rv[j] ? s0 + ri : s0) * g.ldF + 4 * (lane & 15);
+  }
   int c = cb;
   for (; c + 16 * kU <= ce; c += 16 * kU) {
-    float4 fa[kU][2], bv[kU][NG];
+    float4 fv[8], bv[kU][NG];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) load(c + 16 * u + 4 * kq, fa[u], bv[u]);
+    for (int j = 0; j < 8; ++j)
+      fv[j] = rv[j] ? *reinterpret_cast<const float4 *>(rp[j] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) step(fa[u], bv[u]);
+    for (int u = 0; u < kU; ++u) {
+      float4 dummy[2];
+      load(c + 16 * u + 4 * kq, dummy, bv[u]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      *reinterpret_cast<float4 *>(stg + (4 * j + (lane >> 4)) * kSLd + 4 * (lane & 15)) = fv[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      float4 fa[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+        fa[rt] = *reinterpret_cast<const float4 *>(stg + (16 * rt + i_row) * kSLd + 16 * u + 4 * kq);
+      step(fa, bv[u]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   for (; c < ce; c += 16) {
     float4 fa[2], bv[NG];
     load(c + 4 * kq, fa, bv);
     step(fa, bv);
   }
+  __syncthreads();  // every wave is done with its stage: the buffer takes the partial sums
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
