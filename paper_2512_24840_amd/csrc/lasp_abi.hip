@@ -98,7 +98,7 @@ void free_ws(Workspace *w) {
 // on).  Earlier work on the stream may still use old buffers, so the stream
 // is synchronised before anything is freed.
 int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hipStream_t st,
-                   bool lm = false) {
+                   bool lm = false, bool want_order = false) {
   const size_t B = (size_t)g.B;
   const size_t need_hist = B * (size_t)hist_w;
   const size_t need_lm = lm ? B : 0;
@@ -107,7 +107,7 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
   const size_t need_fbar = B * g.ldF;
   const size_t need_basis = (size_t)g.nb * g.ldF;
   const size_t need_tsplit = (size_t)32 * g.ldF;
-  const size_t need_order = hist_w > 0 ? B + 1 : 0;
+  const size_t need_order = (hist_w > 0 || want_order) ? B + 1 : 0;
   const bool regrow = B > w->cap_B || need_ow > w->cap_ow || need_fp > w->cap_fp ||
                       need_fbar > w->cap_fbar || need_basis > w->cap_basis ||
                       need_tsplit > w->cap_tsplit || need_order > w->cap_order ||
@@ -741,7 +741,7 @@ extern "C" {
 size_t lasp_pool_slot_bytes(const lasp_opts *opts, const double *wave_grid) {
   Geometry g;
   if (make_geometry(opts, wave_grid, &g)) return 0;
-  return (size_t)lasp::kNPL * g.block * 8 + (size_t)5 * g.ldF * 4 + 64 + 3 * 20 + 48 +
+  return (size_t)lasp::kNPL * g.block * 8 + (size_t)5 * g.ldF * 4 + 64 + 3 * 20 + 52 +
          (size_t)8 * opts->stop_window;
 }
 
@@ -765,7 +765,7 @@ int lasp_pool_create(const double *wave_grid, const float *basis, const lasp_opt
     delete p;
     return dev_fail(e, "hipGetDevice");
   }
-  rc = ensure_buffers(&p->w, g, 4, opts->stop_window, p->st);
+  rc = ensure_buffers(&p->w, g, 4, opts->stop_window, p->st, false, true);
   if (!rc) {
     e = hipMemsetAsync(p->w.s.target, 0, sizeof(int) * g.B, p->st);
     if (e == hipSuccess) e = hipMemsetAsync(p->w.s.t, 0, sizeof(int) * g.B, p->st);
@@ -807,6 +807,11 @@ int lasp_pool_step(lasp_pool *p, int32_t slot_end, int32_t k) {
   s.fp_stride = g.ldF;
   const lasp::AdamCfg adam{p->opts.lr,  p->opts.beta1,       p->opts.beta2,
                            p->opts.eps, p->opts.stop_window, p->opts.stop_tol};
+  // the slots below their step target, listed so that the step kernels skip
+  // idle and finished slots (a fit's arithmetic does not depend on its place)
+  LASP_CHECK(lasp::launch_compact(g, s, p->w.order, p->w.order + p->g.B, p->st), "active list");
+  s.order = p->w.order;
+  s.n_active = p->w.order + p->g.B;
   for (int it = 0; it < k; ++it) {
     {
       LASP_TIMED(LASP_K_INTERP_FWD, p->st);
