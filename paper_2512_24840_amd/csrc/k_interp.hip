@@ -114,8 +114,9 @@ __device__ inline void fwd_stage(float *sT, int wave, int lane, int n, const flo
 // Row r of the launch (entry r / rps of the work list, derivative row
 // r % rps) lands in F' row spec * rps + r % rps.
 __device__ inline int fwd_dst_row(const State &s, int r, int rps) {
+  if (!s.order) return r;  // no work list: rows in place
   const int e = r / rps;
-  return work_spec(s, e) * rps + (r - e * rps);
+  return s.order[e] * rps + (r - e * rps);
 }
 
 __device__ inline void fwd_store(const Geometry &g, const State &s, const float *sT, int r0,
