@@ -22,6 +22,11 @@ namespace {
 
 constexpr int kFwdTiles = 8;  // 16-pixel tiles per wave in the forward GEMM
 
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
 // Feature row t of spectrum s: t = 0 is phi(u), t = 1..3 is d phi / d u_t.
 __device__ inline void feature_row(const float *u, int t, float *out) {
   const float x = u[0], y = u[1], z = u[2];
@@ -111,16 +116,23 @@ __device__ inline void fwd_stage(float *sT, int wave, int lane, int n, const flo
       make_float4(v[0], v[1], v[2], v[3]);
 }
 
-// Row r of the launch (entry r / rps of the work list, derivative row
-// r % rps) lands in F' row spec * rps + r % rps.
-__device__ inline int fwd_dst_row(const State &s, int r, int rps) {
-  if (!s.order) return r;  // no work list: rows in place
-  const int e = r / rps;
-  return s.order[e] * rps + (r - e * rps);
+// F' rows of the block's 16 launch rows r0 + j: row r (entry r / rps of the
+// work list, derivative row r % rps) lands in F' row spec * rps + r % rps.
+// Threads 0..15 write dst; a barrier must follow before fwd_store.
+__device__ inline void fwd_dst_rows(const State &s, int r0, int rows, int rps, int *dst) {
+  const int j = threadIdx.x;
+  if (j >= 16 || r0 + j >= rows) return;
+  const int r = r0 + j;
+  if (!s.order) {
+    dst[j] = r;  // no work list: rows in place
+  } else {
+    const int e = r / rps;
+    dst[j] = s.order[e] * rps + (r - e * rps);
+  }
 }
 
-__device__ inline void fwd_store(const Geometry &g, const State &s, const float *sT, int r0,
-                                 int rows, int rps) {
+__device__ inline void fwd_store(const Geometry &g, const State &s, const float *sT,
+                                 const int *dst, int r0, int rows) {
   const int c_base = blockIdx.x * kFwdCols;
 #pragma unroll
   for (int q = 0; q < 16 * kFwdCols / 4 / 256; ++q) {
@@ -128,7 +140,7 @@ __device__ inline void fwd_store(const Geometry &g, const State &s, const float 
     const int r = e / (kFwdCols / 4), c4 = e - r * (kFwdCols / 4);
     const int col = c_base + 4 * c4;
     if (r0 + r < rows && col < g.ldF)
-      *reinterpret_cast<float4 *>(s.fp + (size_t)fwd_dst_row(s, r0 + r, rps) * g.ldF + col) =
+      *reinterpret_cast<float4 *>(s.fp + (size_t)dst[r] * g.ldF + col) =
           *reinterpret_cast<const float4 *>(sT + r * kFwdLd + 4 * c4);
   }
 }
@@ -136,6 +148,7 @@ __device__ inline void fwd_store(const Geometry &g, const State &s, const float 
 // BF16x3 variant of k_interp_fwd (same grid and output layout).
 __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, int rows_per_spec, int skip_done) {
   __shared__ __align__(16) float sT[16 * kFwdLd];
+  __shared__ int dst[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rows = work_count(g, s) * rows_per_spec;
   const int r0 = blockIdx.y * 16;
@@ -150,6 +163,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, in
     }
     if (!any) return;
   }
+  fwd_dst_rows(s, r0, rows, rows_per_spec, dst);
   bf16x8 b_hi, b_lo;
   float phi0 = 0.f;
   {
@@ -193,7 +207,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, in
     fwd_stage(sT, wave, lane, n, out);
   }
   __syncthreads();
-  fwd_store(g, s, sT, r0, rows, rows_per_spec);
+  fwd_store(g, s, sT, dst, r0, rows);
 }
 
 // F'[r][c] = sum_k Phi[r][k] basis[k][c] for r < rows (rows = B or 4B with
@@ -202,6 +216,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd_bf16(Geometry g, State s, in
 template <int NB>
 __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int rows_per_spec, int skip_done) {
   __shared__ __align__(16) float sT[16 * kFwdLd];
+  __shared__ int dst[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rows = work_count(g, s) * rows_per_spec;
   const int r0 = blockIdx.y * 16;
@@ -216,6 +231,7 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
     }
     if (!any) return;
   }
+  fwd_dst_rows(s, r0, rows, rows_per_spec, dst);
 
   float bv[NB / 4];
   {
@@ -236,21 +252,47 @@ __global__ __launch_bounds__(256) void k_interp_fwd(Geometry g, State s, int row
     for (int kk = 0; kk < NB / 4; ++kk)
       bv[kk] = kq == 0 ? phi[4 * kk] : (kq == 1 ? phi[4 * kk + 1] : (kq == 2 ? phi[4 * kk + 2] : phi[4 * kk + 3]));
   }
-
   const int cbase = (blockIdx.x * 4 + wave) * (16 * kFwdTiles);
-  for (int n = 0; n < kFwdTiles; ++n) {
-    const int c0 = cbase + 16 * n;
-    if (c0 >= g.ldF) break;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  // products over feature groups KK0 .. KK0 + NKK - 1 (4 features each)
+  auto run = [&](auto kk0, auto nkk) {
+    constexpr int KK0 = decltype(kk0)::value, NKK = decltype(nkk)::value;
+    for (int n = 0; n < kFwdTiles; ++n) {
+      const int c0 = cbase + 16 * n;
+      if (c0 >= g.ldF) break;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < NB / 4; ++kk) {
-      const float a = s.basis[(size_t)(4 * kk + kq) * g.ldF + c0 + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[kk], acc, 0, 0, 0);
+      for (int kk = KK0; kk < KK0 + NKK; ++kk) {
+        const float a = s.basis[(size_t)(4 * kk + kq) * g.ldF + c0 + (lane & 15)];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[kk], acc, 0, 0, 0);
+      }
+      fwd_stage(sT, wave, lane, n, acc);
     }
-    fwd_stage(sT, wave, lane, n, acc);
+  };
+  if constexpr (NB == kNB) {
+    run(IntC<0>{}, IntC<NB / 4>{});
+  } else {
+    // an emulator class whose weight and weight derivative are zero in all
+    // 16 rows of the tile (spectra of other Teff regimes) has an all-zero
+    // feature block; its products would add exact zeros and are left out
+    int mask = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxClasses; ++q) {
+      bool nz = false;
+#pragma unroll
+      for (int kk = 5 * q; kk < 5 * q + 5; ++kk) nz = nz || bv[kk] != 0.f;
+      mask |= (__ballot(nz) != 0) << q;
+    }
+    switch (mask) {  // wave uniform; every wave of the block sees the same rows
+      case 1: run(IntC<0>{}, IntC<5>{}); break;
+      case 2: run(IntC<5>{}, IntC<5>{}); break;
+      case 4: run(IntC<10>{}, IntC<5>{}); break;
+      case 3: run(IntC<0>{}, IntC<10>{}); break;
+      case 6: run(IntC<5>{}, IntC<10>{}); break;
+      default: run(IntC<0>{}, IntC<15>{}); break;
+    }
   }
   __syncthreads();
-  fwd_store(g, s, sT, r0, rows, rows_per_spec);
+  fwd_store(g, s, sT, dst, r0, rows);
 }
 
 // Gradient of J with respect to u from Phi-bar (pb, NB entries) and the
@@ -484,32 +526,35 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
   const int per_wave = g.ldF / NWV;  // ldF is a multiple of 128
   const int cb = wave * per_wave, ce = cb + per_wave;
   constexpr int kU = 4;
-  auto step = [&](const float4 (&fa)[2], const float4 (&bv)[NG]) {
+  // groups Q0 .. Q1 - 1 of 16 basis rows
+  auto step = [&](auto q0, auto q1, const float4 (&fa)[2], const float4 (&bv)[NG]) {
+    constexpr int Q0 = decltype(q0)::value, Q1 = decltype(q1)::value;
     float4 a[2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) a[rt] = row_ok[rt] ? fa[rt] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].x, bv[q].x, acc[rt][q], 0, 0, 0);
+      for (int q = Q0; q < Q1; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].x, bv[q].x, acc[rt][q], 0, 0, 0);
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].y, bv[q].y, acc[rt][q], 0, 0, 0);
+      for (int q = Q0; q < Q1; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].y, bv[q].y, acc[rt][q], 0, 0, 0);
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].z, bv[q].z, acc[rt][q], 0, 0, 0);
+      for (int q = Q0; q < Q1; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].z, bv[q].z, acc[rt][q], 0, 0, 0);
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int q = 0; q < NG; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].w, bv[q].w, acc[rt][q], 0, 0, 0);
+      for (int q = Q0; q < Q1; ++q) acc[rt][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt].w, bv[q].w, acc[rt][q], 0, 0, 0);
   };
-  auto load = [&](int cc, float4 (&fa)[2], float4 (&bv)[NG]) {
+  auto load = [&](auto q0, auto q1, int cc, float4 (&fa)[2], float4 (&bv)[NG]) {
+    constexpr int Q0 = decltype(q0)::value, Q1 = decltype(q1)::value;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) fa[rt] = *reinterpret_cast<const float4 *>(fb_row[rt] + cc);
 #pragma unroll
-    for (int q = 0; q < NG; ++q) {
+    for (int q = Q0; q < Q1; ++q) {
       if (16 * q + 16 <= NB || b_ok[q])
         bv[q] = *reinterpret_cast<const float4 *>(b_ptr[q] + cc);
       else
@@ -528,39 +573,71 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
     rv[j] = s0 + ri < count;
     rp[j] = s.fbar + (size_t)work_spec(s, rv[j] ? s0 + ri : s0) * g.ldF + 4 * (lane & 15);
   }
-  int c = cb;
-  for (; c + 16 * kU <= ce; c += 16 * kU) {
-    float4 fv[8], bv[kU][NG];
+  auto run = [&](auto q0, auto q1) {
+    int c = cb;
+    for (; c + 16 * kU <= ce; c += 16 * kU) {
+      float4 fv[8], bv[kU][NG];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      fv[j] = rv[j] ? *reinterpret_cast<const float4 *>(rp[j] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int j = 0; j < 8; ++j)
+        fv[j] = rv[j] ? *reinterpret_cast<const float4 *>(rp[j] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      float4 dummy[2];
-      load(c + 16 * u + 4 * kq, dummy, bv[u]);
+      for (int u = 0; u < kU; ++u) {
+        float4 dummy[2];
+        load(q0, q1, c + 16 * u + 4 * kq, dummy, bv[u]);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        *reinterpret_cast<float4 *>(stg + (4 * j + (lane >> 4)) * kSLd + 4 * (lane & 15)) = fv[j];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        float4 fa[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+          fa[rt] = *reinterpret_cast<const float4 *>(stg + (16 * rt + i_row) * kSLd + 16 * u + 4 * kq);
+        step(q0, q1, fa, bv[u]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      *reinterpret_cast<float4 *>(stg + (4 * j + (lane >> 4)) * kSLd + 4 * (lane & 15)) = fv[j];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      float4 fa[2];
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-        fa[rt] = *reinterpret_cast<const float4 *>(stg + (16 * rt + i_row) * kSLd + 16 * u + 4 * kq);
-      step(fa, bv[u]);
+    for (; c < ce; c += 16) {
+      float4 fa[2], bv[NG];
+      load(q0, q1, c + 4 * kq, fa, bv);
+      step(q0, q1, fa, bv);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  for (; c < ce; c += 16) {
-    float4 fa[2], bv[NG];
-    load(c + 4 * kq, fa, bv);
-    step(fa, bv);
+  };
+  if constexpr (NB == kNB) {
+    run(IntC<0>{}, IntC<NG>{});
+  } else {
+    // an emulator class with zero weight and weight derivative for all 32
+    // spectra (other Teff regimes) only ever multiplies its rows of
+    // Phi-bar by zero: the 16-row groups that hold no other class's rows
+    // are left out (classes are rows 0-19, 20-39, 40-59; groups 0-15,
+    // 16-31, 32-47, 48-63)
+    bool nz[kMaxClasses] = {false, false, false};
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      if (row_ok[rt]) {
+        float w[kMaxClasses], dw[kMaxClasses];
+        class_weights(g, s.u[(size_t)work_spec(s, s0 + 16 * rt + i_row) * kNP], w, dw);
+#pragma unroll
+        for (int q = 0; q < kMaxClasses; ++q) nz[q] = nz[q] || w[q] != 0.f || dw[q] != 0.f;
+      }
+    }
+    int mask = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxClasses; ++q) mask |= (__ballot(nz[q]) != 0) << q;
+    switch (mask) {  // block uniform: all waves see the same 32 spectra
+      case 1: run(IntC<0>{}, IntC<2>{}); break;
+      case 2: run(IntC<1>{}, IntC<3>{}); break;
+      case 4: run(IntC<2>{}, IntC<4>{}); break;
+      case 3: run(IntC<0>{}, IntC<3>{}); break;
+      case 6: run(IntC<1>{}, IntC<4>{}); break;
+      default: run(IntC<0>{}, IntC<4>{}); break;
+    }
   }
   __syncthreads();  // every wave is done with its stage: the buffer takes the partial sums
 #pragma unroll

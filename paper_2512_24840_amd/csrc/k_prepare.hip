@@ -179,30 +179,69 @@ __global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double
 }
 
 // Steps taken and stopped flag of each slot.
-// The spectra still taking steps, in index order: each thread counts the
-// active spectra of its contiguous chunk, a workgroup-wide scan of the
-// counts gives each chunk's first position, and each thread writes its
-// chunk.  One workgroup of 1024 threads.
+// The spectra still taking steps, in index order within each Teff regime
+// (with several emulator classes: cool, cool/warm blend, warm, warm/hot
+// blend, hot, from the current parameters), regimes in that order, so that
+// the contraction tiles mostly hold one regime.  Each thread counts the
+// active spectra of its contiguous chunk per regime, workgroup-wide scans of
+// the counts give each chunk's first position in each regime, and each
+// thread writes its chunk.  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_compact(Geometry g, State s, int *order,
                                                   int *n_active) {
-  __shared__ int cnt[1024];
+  constexpr int kKeys = 5;
+  __shared__ int cnt[kKeys][1024];
+  __shared__ int first[kKeys + 1];
   const int t = threadIdx.x;
+  const int nk = g.n_classes > 1 ? kKeys : 1;
+  // regime boundaries in the normalised log Teff coordinate
+  double ue[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) ue[e] = (log10(g.edges[e]) - g.lt_lo) / g.lt_half - 1.0;
+  auto key = [&](int i) {
+    if (nk == 1) return 0;
+    const double u1 = s.u[(size_t)i * kNP];
+    int k = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) k += u1 > ue[e] ? 1 : 0;
+    return k;
+  };
   const int chunk = (g.B + 1023) / 1024;
   const int b0 = min(t * chunk, g.B), b1 = min(b0 + chunk, g.B);
-  int c = 0;
-  for (int i = b0; i < b1; ++i) c += slot_active(s, i) ? 1 : 0;
-  cnt[t] = c;
+  int c[kKeys] = {0, 0, 0, 0, 0};
+  for (int i = b0; i < b1; ++i) {
+    if (!slot_active(s, i)) continue;
+    const int k = key(i);
+#pragma unroll
+    for (int q = 0; q < kKeys; ++q) c[q] += q == k ? 1 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < kKeys; ++q) cnt[q][t] = c[q];
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
-    const int v = t >= off ? cnt[t - off] : 0;
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scans
+    int v[kKeys];
+#pragma unroll
+    for (int q = 0; q < kKeys; ++q) v[q] = (t >= off && q < nk) ? cnt[q][t - off] : 0;
     __syncthreads();
-    cnt[t] += v;
+#pragma unroll
+    for (int q = 0; q < kKeys; ++q) cnt[q][t] += v[q];
     __syncthreads();
   }
-  int pos = cnt[t] - c;
-  for (int i = b0; i < b1; ++i)
-    if (slot_active(s, i)) order[pos++] = i;
-  if (t == 1023) *n_active = cnt[1023];
+  if (t == 0) {
+    first[0] = 0;
+    for (int q = 0; q < kKeys; ++q) first[q + 1] = first[q] + cnt[q][1023];
+  }
+  __syncthreads();
+  int pos[kKeys];
+#pragma unroll
+  for (int q = 0; q < kKeys; ++q) pos[q] = first[q] + cnt[q][t] - c[q];
+  for (int i = b0; i < b1; ++i) {
+    if (!slot_active(s, i)) continue;
+    const int k = key(i);
+#pragma unroll
+    for (int q = 0; q < kKeys; ++q)
+      if (q == k) order[pos[q]++] = i;
+  }
+  if (t == 1023) *n_active = first[kKeys];
 }
 
 __global__ void k_progress(Geometry g, State s, int32_t *steps, int32_t *done) {

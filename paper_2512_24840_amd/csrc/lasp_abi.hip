@@ -176,7 +176,7 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
 }
 
 int get_workspace(const Geometry &g, int fp_rows, int hist_w, hipStream_t st, Workspace **out,
-                  bool lm = false) {
+                  bool lm = false, bool want_order = false) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
@@ -189,7 +189,7 @@ int get_workspace(const Geometry &g, int fp_rows, int hist_w, hipStream_t st, Wo
     w->stream = st;
     g_ws[key] = w;
   }
-  int rc = ensure_buffers(w, g, fp_rows, hist_w, st, lm);
+  int rc = ensure_buffers(w, g, fp_rows, hist_w, st, lm, want_order);
   if (rc) return rc;
   *out = w;
   return LASP_OK;
@@ -487,7 +487,10 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   const int W = opts->stop_window;
   const int polish = opts->polish_iters;
   const int ce = opts->clean_every, cm = opts->clean_max;
-  rc = get_workspace(g, (out_cov || polish) ? 4 : 1, W, st, &w, polish > 0);
+  // several emulator classes: the work list also groups the spectra by Teff
+  // regime (tiles of one regime skip the other classes' products)
+  const bool regimes = g.n_classes > 1;
+  rc = get_workspace(g, (out_cov || polish) ? 4 : 1, W, st, &w, polish > 0, regimes);
   if (rc) return rc;
   if (ce > 0) {
     const size_t need = (size_t)g.B * g.P;
@@ -528,7 +531,7 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
     if (e != hipSuccess) return dev_fail(e, "active-list events");
   }
   for (int it = 0; it < n_steps; ++it) {
-    if (W > 0 && it > 0 && it % kCompactEvery == 0) {
+    if ((W > 0 || regimes) && (it > 0 || regimes) && it % kCompactEvery == 0) {
       // the spectra still stepping, listed so that the per-step kernels cover
       // those only (a fit's arithmetic does not depend on its place)
       State all = s;
@@ -536,6 +539,8 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
       LASP_CHECK(lasp::launch_compact(g, all, w->order, w->order + g.B, st), "active list");
       s.order = w->order;
       s.n_active = w->order + g.B;
+    }
+    if (W > 0 && it > 0 && it % kCompactEvery == 0) {
       // once no fit is active, stop enqueuing steps: the host reads the list
       // length of the previous compaction, whose steps the device is still
       // working through, so the wait leaves no gap

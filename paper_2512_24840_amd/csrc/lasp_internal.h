@@ -144,8 +144,10 @@ __device__ inline int work_count(const Geometry &g, const State &s) {
 }
 __device__ inline int work_spec(const State &s, int i) { return s.order ? s.order[i] : i; }
 #endif
-// Writes the spectra with slot_active true, in index order, to order and
-// their number to n_active (one workgroup).
+// Writes the spectra with slot_active true to order -- in index order, or
+// with several emulator classes in index order within each Teff regime,
+// regimes by increasing Teff -- and their number to n_active (one
+// workgroup).
 hipError_t launch_compact(const Geometry &g, const State &s, int *order, int *n_active,
                           hipStream_t st);
 hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, int bf16x3,

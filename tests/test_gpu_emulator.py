@@ -88,6 +88,46 @@ def test_resample_many_rows_ragged_width_and_constant_rows():
     np.testing.assert_allclose(got[::100], 1.0, rtol=2 * np.finfo(np.float32).eps)
 
 
+@pytest.mark.parametrize("ratio", [6, 12, 24, 34, 70])
+def test_resample_every_staged_window_size(ratio):
+    # target bins of about `ratio` source pixels: the 256-pixel blocks of the
+    # tiled kernel stage windows of about 256 * ratio source pixels, which
+    # selects each of its window sizes (2048, 4096, 8192, 12288 pixels) and,
+    # at 70, the direct form; 700 target pixels leave a ragged last block
+    rng = np.random.default_rng(100 + ratio)
+    lam0, dlam, n_out = 4000.0, 0.05, 700
+    lg0 = math.log10(4003.0)
+    d = ratio * dlam / (4003.0 * math.log(10.0))
+    n_src = int((10.0 ** (lg0 + (n_out - 0.5) * d) - (lam0 - dlam / 2)) / dlam) + 10
+    src = rng.uniform(0.2, 2.0, (300, n_src)).astype(np.float32)
+    say(f"[resample] 300 rows x {n_src} -> {n_out} (bins of ~{ratio} source pixels)")
+    got = lasp.resample(to_dev(src), lam0, dlam, n_out, lg0, d)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    ref, ok = oracle.resample(src, lam0, dlam, n_out, lg0, d)
+    assert ok
+    bound = resample_bound(src, lam0, dlam, n_out, lg0, d, ref)
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_resample_coarse_target_bins_wider_than_the_staged_window():
+    # target bins of about 920 source pixels: a chunk of target pixels spans
+    # more source pixels than the tiled kernel stages in LDS, so the direct
+    # form runs; results obey the same bound
+    rng = np.random.default_rng(8)
+    lam0, dlam, n_src, n_out = 4000.0, 0.01, 30000, 28
+    src = rng.uniform(0.2, 2.0, (50, n_src)).astype(np.float32)
+    lg0, d = math.log10(4006.0), 1e-3
+    say(f"[resample] 50 rows x {n_src} -> {n_out} (coarse bins)")
+    got = lasp.resample(to_dev(src), lam0, dlam, n_out, lg0, d)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    ref, ok = oracle.resample(src, lam0, dlam, n_out, lg0, d)
+    assert ok
+    bound = resample_bound(src, lam0, dlam, n_out, lg0, d, ref)
+    assert np.all(np.abs(got - ref) <= bound)
+
+
 def test_resample_rejects_a_target_outside_the_source():
     src = torch.ones((2, 100), dtype=torch.float32, device=DEV)
     with pytest.raises(lasp.LaspError) as e:
@@ -218,6 +258,32 @@ def test_three_class_pool_equals_grouped_fit():
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), ref.params.cpu().numpy())
     pool.close()
+
+
+@pytest.mark.parametrize("stop_window", [0, 20])
+def test_three_class_fit_does_not_depend_on_the_order_of_the_batch(stop_window):
+    # three-class fits go through a work list grouped by Teff regime, and
+    # contraction tiles of one regime leave out the other classes' products
+    # (which would add exact zeros): a fit's arithmetic must not depend on
+    # the tile it lands in, so a shuffled batch gives bit-identical fits
+    n = 150
+    say(f"[3-class order] lamost1550 B={n} stop_window={stop_window}")
+    shape, cfg, basis3, batch = three_class_case("lamost1550", n, 26)
+    perm = np.random.default_rng(7).permutation(n)
+    kw = dict(margin=shape.margin, degree=shape.degree, n_classes=3, want_cov=True,
+              stop_window=stop_window)
+    grid = wave_grid(shape)
+    a = lasp.fit_group(to_dev(batch.obs), to_dev(batch.ivar), grid, to_dev(basis3),
+                       to_dev(batch.init), 120, **kw)
+    b = lasp.fit_group(to_dev(batch.obs[perm]), to_dev(batch.ivar[perm]), grid, to_dev(basis3),
+                       to_dev(batch.init[perm]), 120, **kw)
+    torch.cuda.synchronize()
+    for f in ("params", "cov", "chi2", "steps"):
+        x, y = getattr(a, f).cpu().numpy(), getattr(b, f).cpu().numpy()
+        assert np.array_equal(x[perm], y), f
+    # the batch spans the cool blend, the warm class and the hot blend
+    teff = a.params.cpu().numpy()[:, 0]
+    assert teff.min() < EDGES[1] and teff.max() > EDGES[2], (teff.min(), teff.max())
 
 
 def test_bf16x3_with_three_classes_is_unsupported():
