@@ -486,8 +486,8 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
                                                       int do_adam, float *grad_out) {
   constexpr int NG = (NB + 15) / 16;
   constexpr int NWV = 8;
-  constexpr int kSLd = 68;                        // staging row stride (floats)
-  constexpr int kStage = 32 * kSLd;               // one wave's [32 rows][64 columns]
+  constexpr int kSLd = 36;                        // staging row stride (floats)
+  constexpr int kStage = 32 * kSLd;               // one wave's [32 rows][32 columns]
   constexpr int kRed = 32 * 16 * NG;              // one wave's partial sums
   constexpr int kBuf = NWV * (kStage > kRed ? kStage : kRed);
   __shared__ __align__(16) float sbuf[kBuf];      // staging, then the partial sums
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
     for (int q = 0; q < NG; ++q) acc[rt][q] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int per_wave = g.ldF / NWV;  // ldF is a multiple of 128
   const int cb = wave * per_wave, ce = cb + per_wave;
-  constexpr int kU = 4;
+  constexpr int kU = 2;  // 16-column MFMA blocks per stage
   // groups Q0 .. Q1 - 1 of 16 basis rows
   auto step = [&](auto q0, auto q1, const float4 (&fa)[2], const float4 (&bv)[NG]) {
     constexpr int Q0 = decltype(q0)::value, Q1 = decltype(q1)::value;
@@ -561,47 +561,60 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
         bv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  // F-bar' goes through this wave's LDS stage, 32 rows x 64 columns at a
-  // time, read with row-contiguous loads (256-byte runs per row); the MFMA
-  // operands (16 rows x 4 columns per lane group) come from LDS
+  // F-bar' goes through this wave's LDS stage, 32 rows x 32 columns at a
+  // time, read with row-contiguous loads (128-byte runs per row); the MFMA
+  // operands (16 rows x 4 columns per lane group) come from LDS.  The next
+  // stage's F-bar' and basis loads are in flight during this stage's
+  // products.
   float *stg = sbuf + wave * kStage;
-  const float *rp[8];
-  bool rv[8];
+  const float *rp[4];
+  bool rv[4];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int ri = 4 * j + (lane >> 4);
+  for (int j = 0; j < 4; ++j) {
+    const int ri = 8 * j + (lane >> 3);
     rv[j] = s0 + ri < count;
-    rp[j] = s.fbar + (size_t)work_spec(s, rv[j] ? s0 + ri : s0) * g.ldF + 4 * (lane & 15);
+    rp[j] = s.fbar + (size_t)work_spec(s, rv[j] ? s0 + ri : s0) * g.ldF + 4 * (lane & 7);
   }
   auto run = [&](auto q0, auto q1) {
-    int c = cb;
-    for (; c + 16 * kU <= ce; c += 16 * kU) {
-      float4 fv[8], bv[kU][NG];
+    auto fetch = [&](int cc, float4 (&fv)[4], float4 (&bv)[kU][NG]) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        fv[j] = rv[j] ? *reinterpret_cast<const float4 *>(rp[j] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int j = 0; j < 4; ++j)
+        fv[j] = rv[j] ? *reinterpret_cast<const float4 *>(rp[j] + cc) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         float4 dummy[2];
-        load(q0, q1, c + 16 * u + 4 * kq, dummy, bv[u]);
+        load(q0, q1, cc + 16 * u + 4 * kq, dummy, bv[u]);
       }
+    };
+    int c = cb;
+    if (c + 16 * kU <= ce) {
+      float4 fv[4], bv[kU][NG];
+      fetch(c, fv, bv);
+      for (; c + 16 * kU <= ce; c += 16 * kU) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        *reinterpret_cast<float4 *>(stg + (4 * j + (lane >> 4)) * kSLd + 4 * (lane & 15)) = fv[j];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int j = 0; j < 4; ++j)
+          *reinterpret_cast<float4 *>(stg + (8 * j + (lane >> 3)) * kSLd + 4 * (lane & 7)) = fv[j];
+        float4 bcur[kU][NG];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        float4 fa[2];
+        for (int u = 0; u < kU; ++u)
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-          fa[rt] = *reinterpret_cast<const float4 *>(stg + (16 * rt + i_row) * kSLd + 16 * u + 4 * kq);
-        step(q0, q1, fa, bv[u]);
+          for (int q = 0; q < NG; ++q) bcur[u][q] = bv[u][q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (c + 32 * kU <= ce) fetch(c + 16 * kU, fv, bv);  // next stage
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          float4 fa[2];
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+            fa[rt] = *reinterpret_cast<const float4 *>(stg + (16 * rt + i_row) * kSLd + 16 * u + 4 * kq);
+          step(q0, q1, fa, bcur[u]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     for (; c < ce; c += 16) {
       float4 fa[2], bv[NG];
