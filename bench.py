@@ -163,6 +163,21 @@ def run_serving(banks, rate, duration, seed=0, n_steps=500, steps_per_tick=25,
     return server, done, wall, where
 
 
+def injection_recovery(params, cov, truth):
+    """Fitted values against the injected truths: median absolute error and
+    the spread of the pulls (fit - truth) / sigma_fit per parameter, sigma
+    from the fit's own covariance; a spread near 1 means the reported
+    errors are the actual ones."""
+    names = ("teff_K", "logg", "feh", "rv_kms")
+    err = params[:, :4] - truth[:, :4]
+    sig = np.sqrt(np.maximum(np.einsum("nii->ni", cov)[:, :4], 0.0))
+    ok = np.all(np.isfinite(err), axis=1) & np.all(sig > 0, axis=1)
+    pull = err[ok] / sig[ok]
+    return {"n": int(ok.sum()),
+            "median_abs_error": {k: float(np.median(np.abs(err[ok, i]))) for i, k in enumerate(names)},
+            "pull_std": {k: float(pull[:, i].std()) for i, k in enumerate(names)}}
+
+
 def main_serving(args):
     banks = serving_banks()
     print("[bench] serving banks ready", file=sys.stderr, flush=True)
@@ -504,6 +519,7 @@ def main():
                                   "14,501-point emulator, convergence-stopped Adam, lr 0.1); "
                                   "different workload, context only"},
         "status_flagged": int((status != 0).sum()),
+        "injection_recovery": injection_recovery(params, res.cov.cpu().numpy(), batch.truth),
     }
     if extra:
         out["early_stop"] = {
