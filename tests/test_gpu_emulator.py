@@ -110,6 +110,33 @@ def test_resample_every_staged_window_size(ratio):
     assert np.all(np.abs(got - ref) <= bound)
 
 
+def test_resample_16384_rows_at_the_resampling_leg_shape_on_sample():
+    # the resampling leg's launch: 16,384 linear-grid rows of 28,054 pixels
+    # (the three-class basis rows on their linear grid, each row with its
+    # own scale and offset) onto the 4,028-column basis grid; 64 rows spread
+    # over the launch against the oracle, the rest for finiteness
+    shape = shape_by_name("lamost3900")
+    lam0, dlam, rows = linear_grid_basis(shape, n_classes=3)
+    B = 16384
+    rng = np.random.default_rng(9)
+    scale = rng.uniform(0.5, 1.5, (B, 1)).astype(np.float32)
+    offset = rng.uniform(-0.2, 0.2, (B, 1)).astype(np.float32)
+    src = rows[np.arange(B) % rows.shape[0]] * scale + offset
+    lg0 = ext_lg0(shape)
+    say(f"[resample] {B} rows x {src.shape[1]} -> {shape.n_ext}")
+    got = lasp.resample(to_dev(src), lam0, dlam, shape.n_ext, lg0, shape.dlog10)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    idx = np.linspace(0, B - 1, 64).astype(int)
+    ref, ok = oracle.resample(src[idx], lam0, dlam, shape.n_ext, lg0, shape.dlog10)
+    assert ok
+    bound = resample_bound(src[idx], lam0, dlam, shape.n_ext, lg0, shape.dlog10, ref)
+    err = np.abs(got[idx].astype(np.float64) - ref)
+    say(f"  max err/bound on the sample {np.max(err / bound):.3g}")
+    assert np.all(err <= bound)
+
+
 def test_resample_coarse_target_bins_wider_than_the_staged_window():
     # target bins of about 920 source pixels: a chunk of target pixels spans
     # more source pixels than the tiled kernel stages in LDS, so the direct
