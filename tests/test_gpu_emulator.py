@@ -287,6 +287,31 @@ def test_three_class_pool_equals_grouped_fit():
     pool.close()
 
 
+def test_three_class_fit_16384x3900_matches_oracle_adam_on_sample():
+    # the three-class leg's launch: 16,384 spectra x 3,900 px, 500 Adam
+    # steps on the regime-ordered work list; 32 fits spread over the group
+    # against the oracle's FP64 Adam with the same settings
+    from synth import make_spectra_parallel
+    shape = shape_by_name("lamost3900")
+    basis3, lines3 = make_basis(shape, n_classes=3)
+    B = 16384
+    batch = make_spectra_parallel(shape, lines3, 41, 0, B)
+    say(f"[3-class full size] lamost3900 B={B}, 500 steps; oracle Adam on 32")
+    res = lasp.fit_group(to_dev(batch.obs), to_dev(batch.ivar), wave_grid(shape), to_dev(basis3),
+                         to_dev(batch.init), 500, margin=shape.margin, degree=shape.degree,
+                         n_classes=3)
+    torch.cuda.synchronize()
+    params = res.params.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(params))
+    idx = np.linspace(0, B - 1, 32).astype(int)
+    cfg = oracle.Config.from_shape(shape, BOX_LO, BOX_HI, n_classes=3)
+    ref = oracle.adam_fit_many(cfg, batch.obs[idx], batch.ivar[idx], basis3, batch.init[idx],
+                               n_max=500)
+    err = np.abs(params[idx] - np.array([r["params"] for r in ref]))[:, :4]
+    say(f"  max |GPU - oracle Adam| {err.max(axis=0)}")
+    assert np.all(err <= FIT_TOL), err.max(axis=0)
+
+
 @pytest.mark.parametrize("stop_window", [0, 20])
 def test_three_class_fit_does_not_depend_on_the_order_of_the_batch(stop_window):
     # three-class fits go through a work list grouped by Teff regime, and
