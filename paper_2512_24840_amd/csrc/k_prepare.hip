@@ -23,21 +23,22 @@ __device__ inline float funkey(uint32_t k) {
   return __uint_as_float(b);
 }
 
+// Key of a pixel left out of the selection (no finite flux maps to it).
+constexpr uint32_t kNoKey = 0xffffffffu;
+
 // k-th smallest (0-based) flux among the valid pixels of one spectrum, by a
-// four-pass 8-bit radix select over the order-preserving keys.
-__device__ float block_select(const float *obs, const float *ivar, int P, uint32_t k,
-                              uint32_t *hist, uint32_t *sh) {
+// four-pass 8-bit radix select over the order-preserving keys (staged in
+// LDS, kNoKey for invalid pixels).
+__device__ float block_select(const uint32_t *keys, int P, uint32_t k, uint32_t *hist,
+                              uint32_t *sh) {
   const int tid = threadIdx.x;
   uint32_t prefix = 0, mask = 0;
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (int i = tid; i < 256; i += kPrepBlock) hist[i] = 0;
     __syncthreads();
     for (int j = tid; j < P; j += kPrepBlock) {
-      const float o = obs[j], iv = ivar[j];
-      if (pixel_ok(o, iv)) {
-        const uint32_t key = fkey(o);
-        if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-      }
+      const uint32_t key = keys[j];
+      if (key != kNoKey && (key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
     }
     __syncthreads();
     if (tid == 0) {
@@ -66,6 +67,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
                                                         double bhi1, double bhi2, double bhi3,
                                                         double bhi4, float quantile,
                                                         int init_state, int target_steps) {
+  // [max(P, 2 * 64 * kNPL)]: the row's flux keys, then the layout staging
+  extern __shared__ __align__(16) uint32_t keys[];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sh[2];
   __shared__ int red_n[kPrepBlock / 64];
@@ -80,8 +83,10 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
   int n = 0, bad = 0;
   for (int j = tid; j < g.P; j += kPrepBlock) {
     const float o = o_row[j], iv = i_row[j];
-    n += pixel_ok(o, iv) ? 1 : 0;
+    const bool ok = pixel_ok(o, iv);
+    n += ok ? 1 : 0;
     bad |= (!isfinite(o) || !isfinite(iv)) ? 1 : 0;
+    keys[j] = ok ? fkey(o) : kNoKey;
   }
   n = wave_sum(n);
   bad = wave_sum(bad);
@@ -104,10 +109,10 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
     const float pos = quantile * (float)(n_eff - 1);
     const uint32_t k0 = (uint32_t)floorf(pos);
     const float frac = pos - (float)k0;
-    const float v0 = block_select(o_row, i_row, g.P, k0, hist, sh);
+    const float v0 = block_select(keys, g.P, k0, hist, sh);
     float q = v0;
     if (frac > 0.f && k0 + 1 < (uint32_t)n_eff) {
-      const float v1 = block_select(o_row, i_row, g.P, k0 + 1, hist, sh);
+      const float v1 = block_select(keys, g.P, k0 + 1, hist, sh);
       q = v0 + frac * (v1 - v0);
     }
     if (q > 0.f && isfinite(q)) w = exp2f(rintf(log2f(q)));
@@ -117,18 +122,29 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
   const float w2 = w * w;
 
   // Lane-major layout for the fused pass: slot (i, lane) holds pixel
-  // lane * kNPL + i, so a lane reads its pixels with coalesced loads.
+  // lane * kNPL + i, so a lane reads its pixels with coalesced loads.  The
+  // pixels of 64 lanes at a time go through LDS (the keys' space, free
+  // after the selects): read in pixel order, written in slot order, both
+  // coalesced.
   float2 *dst = s.ow + (size_t)spec * kNPL * g.block;
-  const int slots = kNPL * g.block;
-  for (int q = tid; q < slots; q += kPrepBlock) {
-    const int i = q / g.block, ln = q - i * g.block;
-    const int j = ln * kNPL + i;
-    float2 val = make_float2(0.f, 0.f);
-    if (j < g.P) {
-      const float o = o_row[j], iv = i_row[j];
-      if (pixel_ok(o, iv)) val = make_float2(o * inv_w, iv * w2);
+  float2 *stage = reinterpret_cast<float2 *>(keys);  // [64 * kNPL]
+  constexpr int kChunk = 64 * kNPL;
+  for (int ln0 = 0; ln0 < g.block; ln0 += 64) {
+    __syncthreads();  // the keys, or the previous chunk, are no longer read
+    for (int q = tid; q < kChunk; q += kPrepBlock) {
+      const int j = ln0 * kNPL + q;
+      float2 val = make_float2(0.f, 0.f);
+      if (j < g.P) {
+        const float o = o_row[j], iv = i_row[j];
+        if (pixel_ok(o, iv)) val = make_float2(o * inv_w, iv * w2);
+      }
+      stage[q] = val;
     }
-    dst[q] = val;
+    __syncthreads();
+    for (int q = tid; q < kChunk; q += kPrepBlock) {
+      const int i = q >> 6, l = q & 63;
+      dst[(size_t)i * g.block + ln0 + l] = stage[l * kNPL + i];
+    }
   }
 
   if (tid == 0) {
@@ -280,7 +296,9 @@ hipError_t launch_prepare(const Geometry &g, const State &s, const float *obs, c
                           const float *init_params, const double *lo, const double *hi,
                           float weight_quantile, int init_state, int target_steps,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_prepare, dim3(g.B), dim3(kPrepBlock), 0, st, g, s, obs, ivar, init_params,
+  const size_t lds = sizeof(uint32_t) * (size_t)(g.P > 2 * 64 * kNPL ? g.P : 2 * 64 * kNPL);
+  hipLaunchKernelGGL(k_prepare, dim3(g.B), dim3(kPrepBlock), lds, st,
+                     g, s, obs, ivar, init_params,
                      lo[0], lo[1], lo[2], lo[3], lo[4], hi[0], hi[1], hi[2], hi[3], hi[4],
                      weight_quantile, init_state, target_steps);
   return hipGetLastError();
