@@ -46,8 +46,11 @@ __host__ __device__ inline CovLayout cov_layout(const Geometry &g, int nwaves) {
   return L;
 }
 
+// Two waves per SIMD (two workgroups per CU, as the LDS allows) although the
+// registers then spill some values to scratch: the measured time per
+// launch falls by about a fifth against one wave per SIMD without spills.
 template <int BLOCK, int ND>
-__global__ __launch_bounds__(BLOCK) void k_cov(Geometry g, State s, double blo0, double bhi0,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_cov(Geometry g, State s, double blo0, double bhi0,
                                                double blo1, double bhi1, double blo2, double bhi2,
                                                double out_scale3, double out_scale4,
                                                double *out_cov, float *out_jac,
