@@ -155,6 +155,34 @@ def test_resample_coarse_target_bins_wider_than_the_staged_window():
     assert np.all(np.abs(got - ref) <= bound)
 
 
+def test_resample_strided_rows_through_the_c_abi():
+    # lasp_resample takes row strides: source rows padded to 4,003 floats and
+    # output rows to 341 (row starts off 16-byte boundaries), the padding
+    # left untouched
+    import ctypes
+    rng = np.random.default_rng(11)
+    lam0, dlam, n_src, n_out, rows = 5000.0, 0.05, 4000, 333, 300
+    lds, ldo = n_src + 3, n_out + 8
+    src = rng.uniform(0.2, 2.0, (rows, n_src)).astype(np.float32)
+    lg0, d = math.log10(5010.0), 2e-5
+    padded = np.full((rows, lds), np.nan, np.float32)
+    padded[:, :n_src] = src
+    src_dev = to_dev(padded)
+    out_dev = torch.full((rows, ldo), -7.0, dtype=torch.float32, device=DEV)
+    lib = lasp.lasp.load()
+    rc = lib.lasp_resample(ctypes.c_void_p(src_dev.data_ptr()), rows, n_src, lds, lam0, dlam,
+                           ctypes.c_void_p(out_dev.data_ptr()), n_out, ldo, lg0, d,
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    torch.cuda.synchronize()
+    out = out_dev.cpu().numpy()
+    assert np.all(out[:, n_out:] == -7.0)
+    ref, ok = oracle.resample(src, lam0, dlam, n_out, lg0, d)
+    assert ok
+    bound = resample_bound(src, lam0, dlam, n_out, lg0, d, ref)
+    assert np.all(np.abs(out[:, :n_out] - ref) <= bound)
+
+
 def test_resample_rejects_a_target_outside_the_source():
     src = torch.ones((2, 100), dtype=torch.float32, device=DEV)
     with pytest.raises(lasp.LaspError) as e:
