@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lasp_oracle.c")
 _LIB = os.path.join(_HERE, "liblasp_oracle.so")
 
-NONFINITE, NO_DATA, SINGULAR, CONT_NONPOS, OUT_OF_BOX, NOT_CONVERGED = (1 << i for i in range(6))
+NONFINITE, NO_DATA, SINGULAR, CONT_NONPOS, OUT_OF_BOX, NOT_CONVERGED, SIGMA_FLOOR = (
+    1 << i for i in range(7))
 N_PAR = 5
 N_BASIS = 20
 

@@ -51,6 +51,7 @@ enum {
   ORC_CONT_NONPOS = 1u << 3,
   ORC_OUT_OF_BOX = 1u << 4,
   ORC_NOT_CONVERGED = 1u << 5,
+  ORC_WIDTH_FLOOR = 1u << 6, /* kernel width at the 0.1 px floor in some arm */
 };
 
 typedef struct orc_cfg {
@@ -160,6 +161,7 @@ void orc_convolve(const double *fp, int n_ext, const double *G, int H, int margi
 typedef struct {
   double mu, sig;          /* pixels */
   double dmu_du, dsig_du;  /* d mu / d u4, d sig / d u5 (0 when floored) */
+  int floored;             /* the width sits at the 0.1 px floor */
 } orc_arm_kernel;
 
 static void arm_kernel(const orc_cfg *cfg, const double *u, int arm, orc_arm_kernel *ak) {
@@ -175,13 +177,25 @@ static void arm_kernel(const orc_cfg *cfg, const double *u, int arm, orc_arm_ker
   if (spx < ORC_SIGMA_FLOOR) {
     ak->sig = ORC_SIGMA_FLOOR;
     ak->dsig_du = 0.0;
+    ak->floored = 1;
   } else {
     ak->sig = spx;
     ak->dsig_du = 0.5 * (cfg->hi[4] - cfg->lo[4]) * dseff / scale;
+    ak->floored = 0;
   }
 }
 
 static int arm_count(const orc_cfg *cfg) { return cfg->n_arms > 0 ? cfg->n_arms : 1; }
+
+/* ORC_WIDTH_FLOOR if the width of some arm is floored at u. */
+static unsigned floor_flag(const orc_cfg *cfg, const double *u) {
+  for (int a = 0; a < arm_count(cfg); ++a) {
+    orc_arm_kernel ak;
+    arm_kernel(cfg, u, a, &ak);
+    if (ak.floored) return ORC_WIDTH_FLOOR;
+  }
+  return 0;
+}
 static int arm_begin(const orc_cfg *cfg, int a) { return cfg->n_arms > 0 ? cfg->arm_start[a] : 0; }
 static int arm_end(const orc_cfg *cfg, int a) {
   return (cfg->n_arms > 0 && a + 1 < cfg->n_arms) ? cfg->arm_start[a + 1] : cfg->n_pix;
@@ -444,6 +458,7 @@ int orc_eval(const orc_cfg *cfg, const float *obs, const float *ivar, const floa
   }
   for (int t = 0; t < ORC_NP; ++t)
     if (fabs(u[t]) > 1.5) fl |= ORC_OUT_OF_BOX;
+  fl |= floor_flag(cfg, u);
   if (fp) memcpy(fp, wk.fp, sizeof(double) * ne);
   if (fpp) memcpy(fpp, wk.fpp, sizeof(double) * P);
   if (b_out) memcpy(b_out, b, sizeof(double) * nd);
@@ -619,6 +634,7 @@ int orc_fit(const orc_cfg *cfg, const float *obs, const float *ivar, const float
   if (!converged) fl |= ORC_NOT_CONVERGED;
   for (int t = 0; t < ORC_NP; ++t)
     if (fabs(x[t]) > 1.5) fl |= ORC_OUT_OF_BOX;
+  fl |= floor_flag(cfg, x);
   for (int j = 0; j < cfg->n_pix; ++j)
     if (!(cont_at(cfg, &wk, x + ORC_NP, j) > 0.0)) {
       fl |= ORC_CONT_NONPOS;

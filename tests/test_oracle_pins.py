@@ -378,22 +378,130 @@ def test_covariance_equals_schur_complement_inverse(small_case):
     np.testing.assert_allclose(res["cov"], jd[:, None] * res["cov_u"] * jd[None, :], rtol=1e-12)
 
 
-def test_covariance_pull_distribution():
+
+@pytest.fixture(scope="module")
+def pull_draws():
+    """400 noise realisations at one fixed truth, each fitted by the oracle."""
     shape = small_shape(P=300, M=32, D=4)
     basis, _ = make_basis(shape)
     cfg = cfg_for(shape)
     u_true = np.array([0.2, -0.1, 0.3, 0.1, 0.2])
     b_true = np.array([100.0, 5.0, -3.0, 1.0, 0.5])
-    ivar_val = 1.0 / 2.0 ** 2
-    ivar = np.full(shape.n_pix, ivar_val, np.float32)
+    ivar = np.full(shape.n_pix, 1.0 / 2.0 ** 2, np.float32)
     clean = _noiseless_obs(cfg, shape, basis, u_true, b_true, ivar).astype(np.float64)
     rng = np.random.default_rng(11)
-    pulls = []
+    fits = []
     for _ in range(400):
         obs = (clean + rng.normal(0, 2.0, shape.n_pix)).astype(np.float32)
-        res = oracle.fit(cfg, obs, ivar, basis, u_true)
-        pulls.append((res["u"] - u_true) / np.sqrt(np.diag(res["cov_u"])))
-    pulls = np.array(pulls)
+        fits.append(oracle.fit(cfg, obs, ivar, basis, u_true))
+    return cfg, u_true, fits
+
+
+def test_covariance_pull_distribution(pull_draws):
+    _, u_true, fits = pull_draws
+    pulls = np.array([(r["u"] - u_true) / np.sqrt(np.diag(r["cov_u"])) for r in fits])
     std = pulls.std(axis=0)
     assert np.all(np.abs(std - 1.0) < 0.12), std
     assert np.all(np.abs(pulls.mean(axis=0)) < 0.2)
+
+
+def test_covariance_pull_distribution_in_physical_units(pull_draws):
+    """Section 2.2 stage 9 in the units the fit reports: the spread of the
+    fitted Teff (K), log g, [Fe/H], RV (km/s) and sigma (km/s) around the
+    truth over noise draws equals the covariance's standard deviations.  The
+    physical parameters are the decoded fits, so a wrong Teff or ln 10
+    factor in the covariance's mapping shifts the Teff spread away from 1."""
+    cfg, u_true, fits = pull_draws
+    theta_true = cfg.physical(u_true)
+    pulls = np.array([(r["params"] - theta_true) / np.sqrt(np.diag(r["cov"])) for r in fits])
+    std = pulls.std(axis=0)
+    assert np.all(np.abs(std - 1.0) < 0.12), std
+    assert np.all(np.abs(pulls.mean(axis=0)) < 0.2)
+    # the Teff column differs from the u-space one by T ln 10 times the half
+    # width: a factor of about 2000 here, so the check is not vacuous
+    r = fits[0]
+    assert r["cov"][0, 0] / r["cov_u"][0, 0] > 1e5
+
+
+# ------------------------------------------------------ status flags ------
+
+def test_width_floor_flag_and_zero_derivative():
+    """Reading of Eq. 5 at small widths: sigma_px = max(sigma / (c ln10 dlog10),
+    0.1), flagged, with d chi2 / d sigma = 0 below the floor; the model does
+    not depend on sigma there."""
+    shape = small_shape()
+    basis, lines = make_basis(shape)
+    cfg = cfg_for(shape)
+    b = make_spectra(shape, lines, 31, 0, 1)
+    scale = C_KMS * math.log(10.0) * shape.dlog10
+    u = cfg.normalise(b.init[0])
+    models = []
+    for sigma in (2.0, 4.0, 0.1 * scale * 0.999, 0.1 * scale * 1.001, 60.0):
+        uu = u.copy()
+        uu[4] = 2.0 * (sigma - BOX_LO[4]) / (BOX_HI[4] - BOX_LO[4]) - 1.0
+        r = oracle.evaluate(cfg, b.obs[0], b.ivar[0], basis, uu)
+        floored = sigma / scale < 0.1
+        assert bool(r["flags"] & oracle.SIGMA_FLOOR) == floored, sigma
+        if floored:
+            assert r["grad"][4] == 0.0
+            models.append(r["model"])
+        else:
+            assert r["grad"][4] != 0.0
+    np.testing.assert_array_equal(models[0], models[1])
+    np.testing.assert_array_equal(models[0], models[2])
+
+
+def test_width_floor_flag_per_arm():
+    """With spectrograph arms each arm's width sqrt(sigma^2 + sigma_arm^2)
+    is floored on its own; the flag marks any floored arm."""
+    shape = small_shape(P=300, M=32, D=4, arm_start=(0, 100, 200),
+                        arm_sigma_kms=(0.0, 40.0, 0.0))
+    basis, lines = make_basis(shape)
+    cfg = cfg_for(shape)
+    b = make_spectra(shape, lines, 32, 0, 1)
+    scale = C_KMS * math.log(10.0) * shape.dlog10
+    u = cfg.normalise(b.init[0])
+    for sigma, expect in ((3.0, True), (0.2 * scale, False)):
+        uu = u.copy()
+        uu[4] = 2.0 * (sigma - BOX_LO[4]) / (BOX_HI[4] - BOX_LO[4]) - 1.0
+        r = oracle.evaluate(cfg, b.obs[0], b.ivar[0], basis, uu)
+        assert bool(r["flags"] & oracle.SIGMA_FLOOR) == expect
+        # the unfloored middle arm still depends on sigma
+        assert r["grad"][4] != 0.0
+
+
+def test_out_of_box_flag_threshold():
+    shape = small_shape()
+    basis, lines = make_basis(shape)
+    cfg = cfg_for(shape)
+    b = make_spectra(shape, lines, 33, 0, 1)
+    u = np.array([0.1, -0.2, 0.3, 0.0, 0.1])
+    for t in range(5):
+        for val, expect in ((1.5, False), (-1.5, False), (1.5001, True), (-1.6, True)):
+            uu = u.copy()
+            uu[t] = val
+            r = oracle.evaluate(cfg, b.obs[0], b.ivar[0], basis, uu)
+            assert bool(r["flags"] & oracle.OUT_OF_BOX) == expect, (t, val)
+
+
+def test_nonpositive_continuum_flag_matches_lstsq_sign():
+    """CONT_NONPOS is set when the weighted least-squares continuum (numpy
+    lstsq on the sqrt(W)-scaled Legendre design) is <= 0 at some pixel."""
+    shape = small_shape(P=300, M=32, D=6)
+    basis, lines = make_basis(shape)
+    cfg = cfg_for(shape)
+    b = make_spectra(shape, lines, 34, 0, 2)
+    P = shape.n_pix
+    x = -1.0 + 2.0 * np.arange(P) / P
+    V = np.stack([scipy.special.eval_legendre(n, x) for n in range(shape.degree + 1)], axis=1)
+    for i, negate in ((0, False), (1, True)):
+        obs = b.obs[i].copy()
+        if negate:
+            obs[: P // 5] *= -0.3
+        u = cfg.normalise(b.init[i])
+        r = oracle.evaluate(cfg, obs, b.ivar[i], basis, u)
+        w = b.ivar[i].astype(np.float64)
+        A = np.sqrt(w)[:, None] * r["fpp"][:, None] * V
+        coef = np.linalg.lstsq(A, np.sqrt(w) * obs.astype(np.float64), rcond=None)[0]
+        cont = V @ coef
+        assert bool(r["flags"] & oracle.CONT_NONPOS) == bool(cont.min() <= 0.0) == negate
