@@ -49,13 +49,23 @@ extern "C" {
 #define LASP_E_UNSUPPORTED (-5) /* shape/precision without a compiled kernel */
 
 /* Per-spectrum status bits (opts->status).  One spectrum's status never
- * changes another spectrum's results. */
+ * changes another spectrum's results.
+ *  Input bits, from obs and ivar: NONFINITE_INPUT, NO_DATA.
+ *  Evaluation bits, at the parameters the call returns (lasp_fit_group,
+ *  lasp_pool_finish) or evaluates (lasp_forward); a condition met only at
+ *  intermediate points of a fit is not reported: SINGULAR, CONT_NONPOS,
+ *  OUT_OF_BOX, SIGMA_FLOOR.  CONT_NONPOS is the failed-fit test of the
+ *  paper's Section 4.2 (a nonpositive multiplicative correction P(x) b,
+ *  Step 5 of Section 2.2).
+ *  Course-of-fit bits: STOP_FLAT, STOP_RISING, NOT_CONVERGED, POLISH_LIMIT. */
 #define LASP_ST_NONFINITE_INPUT 0x01u /* some obs/ivar not finite: pixel weight set to 0 */
 #define LASP_ST_NO_DATA 0x02u         /* n_eff <= 5 + degree + 1 */
-#define LASP_ST_SINGULAR 0x04u        /* continuum normal equations not positive definite */
+#define LASP_ST_SINGULAR 0x04u        /* continuum normal equations (or, with a covariance
+                                         requested, its Schur complement) not positive definite */
 #define LASP_ST_CONT_NONPOS 0x08u     /* fitted continuum P(x) b <= 0 at some pixel */
-#define LASP_ST_OUT_OF_BOX 0x10u      /* final |u_t| > 1.5 for some parameter */
-#define LASP_ST_SIGMA_FLOOR 0x20u     /* broadening width at the 0.1 px floor */
+#define LASP_ST_OUT_OF_BOX 0x10u      /* |u_t| > 1.5 (or not finite) for some parameter */
+#define LASP_ST_SIGMA_FLOOR 0x20u     /* broadening width at the 0.1 px floor in some arm
+                                         (d chi2 / d sigma is 0 there) */
 #define LASP_ST_STOP_FLAT 0x40u       /* stopped: loss changed < stop_tol over the window */
 #define LASP_ST_STOP_RISING 0x80u     /* stopped: loss rose at every step of the window */
 #define LASP_ST_NOT_CONVERGED 0x100u  /* stopping rules on, step limit reached first */
@@ -117,7 +127,7 @@ extern "C" {
  *                  lowers chi2 by less than 1e-10 relative or moves u by
  *                  less than 1e-7, or when lambda exceeds 1e10
  *                  (LASP_ST_POLISH_LIMIT if the iteration limit came first).  The paper proposes adding curvature
- *                  information to its Adam stage (Section 5); n_steps = 0
+ *                  information to its Adam stage (Section 4.5); n_steps = 0
  *                  with polish_iters > 0 is a plain LM fit.
  *  clean_every, clean_max  the Clean strategy of Section 2.2 (steps 6 and 8):
  *                  after every clean_every Adam steps (at most clean_max

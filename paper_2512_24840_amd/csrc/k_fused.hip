@@ -62,8 +62,14 @@ __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwave
   return L;
 }
 
+// set_status != 0: this pass evaluates the returned parameters; it replaces
+// the evaluation bits (SINGULAR, CONT_NONPOS, SIGMA_FLOOR) of the spectrum's
+// status with those of this pass.  0 (the passes of the Adam steps): the
+// status is left alone, so a condition seen only on the way does not reach
+// the result.
 template <int BLOCK, int ND, bool ADJ, bool MULTI>
-__global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *model_out) {
+__global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *model_out,
+                                                 int set_status) {
   constexpr int NW = BLOCK / 64;
   constexpr int NNU = 2 * ND - 1;  // nu_0 .. nu_{2D}
   constexpr int NMOM = NNU + ND;   // plus r_0 .. r_D
@@ -373,14 +379,16 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       cm = fmin(cm, sRed[w * 64 + 1]);
     }
     s.chi2[spec] = cs;
-    uint32_t st = s.status[spec];
-    if (!ok) st |= kStSingular;
-    if (!(cm > 0.0)) st |= kStContNonpos;
-    for (int a = 0; a < g.n_arms; ++a) {
-      const double seff = g.bare ? sg : sqrt(sg * sg + g.arm_sig2[a]);
-      if (!(seff * g.inv_scale >= (double)kSigmaFloorPx)) st |= kStSigmaFloor;
+    if (set_status) {
+      uint32_t st = s.status[spec] & ~(kStSingular | kStContNonpos | kStSigmaFloor);
+      if (!ok) st |= kStSingular;
+      if (!(cm > 0.0)) st |= kStContNonpos;
+      for (int a = 0; a < g.n_arms; ++a) {
+        const double seff = g.bare ? sg : sqrt(sg * sg + g.arm_sig2[a]);
+        if (!(seff * g.inv_scale >= (double)kSigmaFloorPx)) st |= kStSigmaFloor;
+      }
+      s.status[spec] = st;
     }
-    s.status[spec] = st;
   }
   if (!ADJ) return;
 
@@ -537,35 +545,36 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
 }
 
 template <int BLOCK, int ND, bool ADJ, bool MULTI>
-hipError_t launch_fused_k(const Geometry &g, const State &s, float *model_out, hipStream_t st) {
+hipError_t launch_fused_k(const Geometry &g, const State &s, float *model_out, int set_status,
+                          hipStream_t st) {
   const FusedLayout L = fused_layout(g, BLOCK / 64, 3 * ND - 1);
   auto k = k_fused<BLOCK, ND, ADJ, MULTI>;
   hipError_t e =
       hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, model_out);
+  hipLaunchKernelGGL(k, dim3(g.B), dim3(BLOCK), L.bytes, st, g, s, model_out, set_status);
   return hipGetLastError();
 }
 
 template <int BLOCK, int ND>
 hipError_t launch_fused_t(const Geometry &g, const State &s, int adjoint, float *model_out,
-                          hipStream_t st) {
+                          int set_status, hipStream_t st) {
   const bool multi = g.n_arms > 1;
   if (adjoint)
-    return multi ? launch_fused_k<BLOCK, ND, true, true>(g, s, model_out, st)
-                 : launch_fused_k<BLOCK, ND, true, false>(g, s, model_out, st);
-  return multi ? launch_fused_k<BLOCK, ND, false, true>(g, s, model_out, st)
-               : launch_fused_k<BLOCK, ND, false, false>(g, s, model_out, st);
+    return multi ? launch_fused_k<BLOCK, ND, true, true>(g, s, model_out, set_status, st)
+                 : launch_fused_k<BLOCK, ND, true, false>(g, s, model_out, set_status, st);
+  return multi ? launch_fused_k<BLOCK, ND, false, true>(g, s, model_out, set_status, st)
+               : launch_fused_k<BLOCK, ND, false, false>(g, s, model_out, set_status, st);
 }
 
 template <int BLOCK>
 hipError_t launch_fused_b(const Geometry &g, const State &s, int adjoint, float *model_out,
-                          hipStream_t st) {
+                          int set_status, hipStream_t st) {
   switch (g.nd) {
-    case 5: return launch_fused_t<BLOCK, 5>(g, s, adjoint, model_out, st);
-    case 7: return launch_fused_t<BLOCK, 7>(g, s, adjoint, model_out, st);
-    case 9: return launch_fused_t<BLOCK, 9>(g, s, adjoint, model_out, st);
-    case 11: return launch_fused_t<BLOCK, 11>(g, s, adjoint, model_out, st);
+    case 5: return launch_fused_t<BLOCK, 5>(g, s, adjoint, model_out, set_status, st);
+    case 7: return launch_fused_t<BLOCK, 7>(g, s, adjoint, model_out, set_status, st);
+    case 9: return launch_fused_t<BLOCK, 9>(g, s, adjoint, model_out, set_status, st);
+    case 11: return launch_fused_t<BLOCK, 11>(g, s, adjoint, model_out, set_status, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -582,11 +591,11 @@ size_t fused_smem_bytes(const Geometry &g) {
 }
 
 hipError_t launch_fused(const Geometry &g, const State &s, int adjoint, float *model_out,
-                        hipStream_t st) {
+                        int set_status, hipStream_t st) {
   switch (g.block) {
-    case 128: return launch_fused_b<128>(g, s, adjoint, model_out, st);
-    case 256: return launch_fused_b<256>(g, s, adjoint, model_out, st);
-    case 512: return launch_fused_b<512>(g, s, adjoint, model_out, st);
+    case 128: return launch_fused_b<128>(g, s, adjoint, model_out, set_status, st);
+    case 256: return launch_fused_b<256>(g, s, adjoint, model_out, set_status, st);
+    case 512: return launch_fused_b<512>(g, s, adjoint, model_out, set_status, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,6 +1,6 @@
-// Levenberg-Marquardt polish of the grouped fit (the curvature step the
-// paper's Section 5 proposes for the Adam stage): per spectrum, damped
-// Gauss-Newton steps on the residual r = sqrt(W) (o - C F'') with the
+// Levenberg-Marquardt polish of the grouped fit (the curvature step that the
+// paper's Section 4.5, future improvements, proposes for the Adam stage): per
+// spectrum, damped Gauss-Newton steps on the residual r = sqrt(W) (o - C F'') with the
 // continuum profiled out.  The covariance kernel supplies the normal
 // equations S du = q at the current u (S = Schur complement of the
 // continuum block of J^T W J, q = Ju^T W e); a step solves

@@ -171,7 +171,16 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
   }
 }
 
-// Physical parameters, status and chi2 at the end of a fit.
+// OUT_OF_BOX of the parameters u (|u_t| > 1.5 for some t, or not finite).
+__device__ inline uint32_t box_bit(const float *u) {
+  uint32_t b = 0;
+  for (int t = 0; t < kNP; ++t)
+    if (!(fabsf(u[t]) <= 1.5f)) b = kStOutOfBox;
+  return b;
+}
+
+// Physical parameters, status and chi2 at the end of a fit.  OUT_OF_BOX is
+// replaced by that of the returned parameters.
 __global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double blo2, double blo3,
                            double blo4, double bhi0, double bhi1, double bhi2, double bhi3,
                            double bhi4, float *out_params, uint32_t *status_out,
@@ -180,10 +189,9 @@ __global__ void k_finalize(Geometry g, State s, double blo0, double blo1, double
   if (spec >= g.B) return;
   const double lo[5] = {blo0, blo1, blo2, blo3, blo4};
   const double hi[5] = {bhi0, bhi1, bhi2, bhi3, bhi4};
-  uint32_t st = s.status[spec];
+  uint32_t st = (s.status[spec] & ~kStOutOfBox) | box_bit(s.u + (size_t)spec * kNP);
   for (int t = 0; t < kNP; ++t) {
     const double u = (double)s.u[(size_t)spec * kNP + t];
-    if (!(fabs(u) <= 1.5)) st |= kStOutOfBox;
     double th = lo[t] + 0.5 * (u + 1.0) * (hi[t] - lo[t]);
     if (t == 0) th = exp10(th);
     out_params[(size_t)spec * kNP + t] = (float)th;
@@ -269,17 +277,20 @@ __global__ void k_progress(Geometry g, State s, int32_t *steps, int32_t *done) {
 }
 
 // Per-spectrum results of a forward evaluation: chi2, the objective
-// J = chi2 / n_eff of Eq. 9 (read per spectrum), n_eff and status.
+// J = chi2 / n_eff of Eq. 9 (read per spectrum), n_eff and status (with
+// OUT_OF_BOX of the evaluated u).
 __global__ void k_outputs(Geometry g, State s, double *chi2_out, float *J_out, int32_t *neff_out,
                           uint32_t *status_out) {
   const int spec = blockIdx.x * blockDim.x + threadIdx.x;
   if (spec >= g.B) return;
   const double c = s.chi2[spec];
   const int n = s.neff[spec];
+  const uint32_t st = (s.status[spec] & ~kStOutOfBox) | box_bit(s.u + (size_t)spec * kNP);
+  s.status[spec] = st;
   if (chi2_out) chi2_out[spec] = c;
   if (J_out) J_out[spec] = n > 0 ? (float)(c / (double)n) : 0.f;
   if (neff_out) neff_out[spec] = n;
-  if (status_out) status_out[spec] = s.status[spec];
+  if (status_out) status_out[spec] = st;
 }
 
 }  // namespace

@@ -564,13 +564,13 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
       State sc = s;
       sc.order = nullptr;
       sc.n_active = nullptr;
-      LASP_CHECK(lasp::launch_fused(g, sc, 0, w->model, st), "fused pass (model)");
+      LASP_CHECK(lasp::launch_fused(g, sc, 0, w->model, 0, st), "fused pass (model)");
       lasp::CleanArgs ca{obs, ivar, w->model, it == ce ? 0.5f : 0.2f, opts->out_mask, nullptr, sc};
       LASP_CHECK(lasp::launch_clean(g, ca, st), "Clean mask");
     }
     {
       LASP_TIMED(LASP_K_FUSED, st);
-      LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, st), "fused pass");
+      LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, 0, st), "fused pass");
     }
     {
       LASP_TIMED(LASP_K_INTERP_BWD, st);
@@ -602,13 +602,13 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
       }
       LASP_CHECK(lasp::launch_lm_solve(g, s, lm, st), "polish step");
       LASP_CHECK(lasp::launch_interp_fwd(g, trial, 0, bf16, st), "interpolator contraction");
-      LASP_CHECK(lasp::launch_fused(g, trial, 0, nullptr, st), "fused pass");
+      LASP_CHECK(lasp::launch_fused(g, trial, 0, nullptr, 1, st), "fused pass");
       LASP_CHECK(lasp::launch_lm_accept(g, s, lm, it == polish - 1, st), "polish accept");
     }
   }
   s.fp_stride = out_cov ? 4 * g.ldF : g.ldF;
   LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, bf16, st), "interpolator contraction");
-  LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, st), "fused pass");
+  LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, 1, st), "fused pass");
   if (out_cov) {
     LASP_TIMED(LASP_K_COV, st);
     LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, nullptr, nullptr, nullptr, st),
@@ -705,7 +705,7 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid, c
   }
   {
     LASP_TIMED(LASP_K_FUSED, st);
-    LASP_CHECK(lasp::launch_fused(g, s, out_grad ? 1 : 0, out_model, st), "fused pass");
+    LASP_CHECK(lasp::launch_fused(g, s, out_grad ? 1 : 0, out_model, 1, st), "fused pass");
   }
   if (out_grad) {
     LASP_TIMED(LASP_K_INTERP_BWD, st);
@@ -824,7 +824,7 @@ int lasp_pool_step(lasp_pool *p, int32_t slot_end, int32_t k) {
     }
     {
       LASP_TIMED(LASP_K_FUSED, p->st);
-      LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, p->st), "fused pass");
+      LASP_CHECK(lasp::launch_fused(g, s, 1, nullptr, 0, p->st), "fused pass");
     }
     {
       LASP_TIMED(LASP_K_INTERP_BWD, p->st);
@@ -863,7 +863,7 @@ int lasp_pool_finish(lasp_pool *p, int32_t slot0, int32_t count, float *out_para
   s.fp_stride = rows * g.ldF;
   LASP_CHECK(lasp::launch_interp_fwd(g, s, out_cov ? 1 : 0, p->bf16, p->st),
              "interpolator contraction");
-  LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, p->st), "fused pass");
+  LASP_CHECK(lasp::launch_fused(g, s, 0, nullptr, 1, p->st), "fused pass");
   if (out_cov) {
     LASP_TIMED(LASP_K_COV, p->st);
     LASP_CHECK(lasp::launch_cov(g, s, p->opts.box_lo, p->opts.box_hi, out_cov, nullptr, nullptr, nullptr,

@@ -152,8 +152,11 @@ hipError_t launch_compact(const Geometry &g, const State &s, int *order, int *n_
                           hipStream_t st);
 hipError_t launch_interp_fwd(const Geometry &g, const State &s, int deriv_rows, int bf16x3,
                              hipStream_t st);
+// set_status: 1 for a pass at the parameters a call returns (the
+// evaluation bits of the status are replaced), 0 for the passes of the
+// steps (status untouched).
 hipError_t launch_fused(const Geometry &g, const State &s, int adjoint, float *model_out,
-                        hipStream_t st);
+                        int set_status, hipStream_t st);
 hipError_t launch_interp_bwd(const Geometry &g, const State &s, const AdamCfg *adam,
                              float *grad_out, int bf16x3, hipStream_t st);
 hipError_t launch_split_basis(const Geometry &g, const State &s, hipStream_t st);

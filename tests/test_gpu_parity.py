@@ -95,11 +95,11 @@ def test_model_jacobian_matches_oracle():
 
 
 def test_fits_alone_match_oracle_lm():
-    say("[fit parity] lamost1550, 16 spectra fitted alone (B=1), 500 Adam steps")
-    shape, cfg, basis, batch = case("lamost1550", 16, config_id=1)
+    say("[fit parity] lamost1550, 64 spectra fitted alone (B=1), 500 Adam steps")
+    shape, cfg, basis, batch = case("lamost1550", 64, config_id=1)
     ref = oracle.fit_many(cfg, batch.obs, batch.ivar, basis, batch.init)
     got = []
-    for i in range(16):
+    for i in range(64):
         r = lasp.fit_group(to_dev(batch.obs[i:i + 1]), to_dev(batch.ivar[i:i + 1]),
                            wave_grid(shape), to_dev(basis), to_dev(batch.init[i:i + 1]), 500,
                            margin=shape.margin, degree=shape.degree)
