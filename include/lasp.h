@@ -224,6 +224,30 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid,
                  double *out_cov, const lasp_opts *opts);
 
 /*
+ * lasp_forward without allocation: the same evaluation and outputs as
+ * lasp_forward (same arguments, same kernels, bitwise the same results), for
+ * callers that cannot allocate device memory -- code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  It calls no
+ * hipMalloc, hipFree or allocating library routine: its scratch (F', F-bar',
+ * the per-spectrum state and the padded basis) lives in one fixed device
+ * array of 64 MiB per device (LASP_NOALLOC_SCRATCH_BYTES), held from the
+ * library's first kernel launch on a device until the process ends.  The
+ * caller still passes every input and output.
+ *  - Sizes: the call returns LASP_E_NOMEM, enqueuing nothing, when B spectra
+ *    of the shape need more than the array; at 3,900 pixels, margin 64, that
+ *    is about 980 spectra (about 570 with out_jac or out_cov).
+ *  - Every call on one device shares that device's array and clears the part
+ *    it uses (with a fill kernel) before using it; calls that overlap on one
+ *    device, on different streams or host threads, race and give undefined
+ *    results.  Calls on one stream are ordered and safe.
+ */
+#define LASP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lasp_forward_noalloc(const float *obs, const float *ivar, const double *wave_grid,
+                         const float *basis, const float *u, float *out_model, double *out_chi2,
+                         float *out_J, int32_t *out_neff, float *out_grad, float *out_jac,
+                         double *out_cov, const lasp_opts *opts);
+
+/*
  * Clean outlier mask (Section 2.2, step 6) of each spectrum from its
  * residual eps = obs - model, in three steps:
  *   B  |eps_j| - f_shift G_j > k sigma, with G_j = max |model_j - model_{j+-1}|

@@ -403,6 +403,119 @@ constexpr int kCompactEvery = 16;
     if (e_ != hipSuccess) return dev_fail(e_, what); \
   } while (0)
 
+// Launch sequence of a forward evaluation at fixed u on the buffers of s
+// (fp rows: 4 when the Jacobian or covariance is wanted, else 1).
+int forward_enqueue(const Geometry &g, State s, const float *obs, const float *ivar,
+                    const float *basis, const float *u, float *out_model, double *out_chi2,
+                    float *out_J, int32_t *out_neff, float *out_grad, float *out_jac,
+                    double *out_cov, const lasp_opts *opts) {
+  hipStream_t st = (hipStream_t)opts->stream;
+  const bool rows4 = out_jac || out_cov;
+  s.target = nullptr;
+  const int bf16 = opts->precision == LASP_PREC_BF16X3;
+  int rc = copy_basis(g, s, basis, bf16, st);
+  if (rc) return rc;
+  {
+    LASP_TIMED(LASP_K_PREPARE, st);
+    LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, nullptr, opts->box_lo, opts->box_hi,
+                                    opts->weight_quantile, 0, 0, st),
+               "prepare");
+  }
+  LASP_CHECK(hipMemcpyAsync(s.u, u, sizeof(float) * lasp::kNP * g.B, hipMemcpyDeviceToDevice, st),
+             "copy u");
+  s.fp_stride = rows4 ? 4 * g.ldF : g.ldF;
+  {
+    LASP_TIMED(LASP_K_INTERP_FWD, st);
+    LASP_CHECK(lasp::launch_interp_fwd(g, s, rows4 ? 1 : 0, bf16, st), "interpolator contraction");
+  }
+  {
+    LASP_TIMED(LASP_K_FUSED, st);
+    LASP_CHECK(lasp::launch_fused(g, s, out_grad ? 1 : 0, out_model, 1, st), "fused pass");
+  }
+  if (out_grad) {
+    LASP_TIMED(LASP_K_INTERP_BWD, st);
+    LASP_CHECK(lasp::launch_interp_bwd(g, s, nullptr, out_grad, bf16, st), "adjoint contraction");
+  }
+  if (rows4) {
+    LASP_TIMED(LASP_K_COV, st);
+    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, out_jac, nullptr, nullptr, st),
+               "covariance / model Jacobian");
+  }
+  LASP_CHECK(lasp::launch_outputs(g, s, out_chi2, out_J, out_neff, opts->status, st), "outputs");
+  return LASP_OK;
+}
+
+// ---- fixed scratch of the allocation-free forward evaluation ----------------
+// One array per device, held from the library's first kernel launch on that
+// device until the process ends.  Host code never passes the array's name to
+// a kernel or a copy: it passes the device address that hipGetSymbolAddress
+// returns for the current device.
+constexpr size_t kScratchBytes = LASP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current).
+int scratch_address(unsigned char **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LASP_E_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return dev_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return LASP_OK;
+}
+
+// Lays the buffers of a forward evaluation (fp_rows rows of F' per spectrum)
+// out back to back from base, each 256-byte aligned, and returns the bytes
+// they take; base == nullptr only measures.
+size_t carve_forward_state(const Geometry &g, int fp_rows, int bf16, unsigned char *base,
+                           State *s) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    void *p = base ? (void *)(base + off) : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t B = (size_t)g.B, ld = (size_t)g.ldF;
+  *s = State{};
+  s->u = (float *)take(B * lasp::kNP * sizeof(float));
+  s->m = (float *)take(B * lasp::kNP * sizeof(float));
+  s->v = (float *)take(B * lasp::kNP * sizeof(float));
+  s->t = (int *)take(B * sizeof(int));
+  s->wscale = (float *)take(B * sizeof(float));
+  s->neff = (int *)take(B * sizeof(int));
+  s->status = (uint32_t *)take(B * sizeof(uint32_t));
+  s->g45 = (float *)take(B * 2 * sizeof(float));
+  s->chi2 = (double *)take(B * sizeof(double));
+  s->ow = (float2 *)take(B * lasp::kNPL * g.block * sizeof(float2));
+  s->fp = (float *)take(B * fp_rows * ld * sizeof(float));
+  s->fbar = (float *)take(B * ld * sizeof(float));
+  s->basis = (float *)take((size_t)g.nb * ld * sizeof(float));
+  if (bf16) {
+    s->basis_hi = (uint16_t *)take((size_t)g.nb * ld * sizeof(uint16_t));
+    s->basis_lo = (uint16_t *)take((size_t)g.nb * ld * sizeof(uint16_t));
+    s->basis_thi = (uint16_t *)take((size_t)32 * ld * sizeof(uint16_t));
+    s->basis_tlo = (uint16_t *)take((size_t)32 * ld * sizeof(uint16_t));
+  }
+  return off;
+}
+
+__global__ void k_zero16(uint4 *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 }  // namespace
 
 extern "C" {
@@ -685,39 +798,46 @@ int lasp_forward(const float *obs, const float *ivar, const double *wave_grid, c
   Workspace *w = nullptr;
   rc = get_workspace(g, rows4 ? 4 : 1, 0, st, &w);
   if (rc) return rc;
-  State s = w->s;
-  s.target = nullptr;
-  const int bf16 = opts->precision == LASP_PREC_BF16X3;
-  rc = copy_basis(g, s, basis, bf16, st);
+  return forward_enqueue(g, w->s, obs, ivar, basis, u, out_model, out_chi2, out_J, out_neff,
+                         out_grad, out_jac, out_cov, opts);
+}
+
+int lasp_forward_noalloc(const float *obs, const float *ivar, const double *wave_grid,
+                         const float *basis, const float *u, float *out_model, double *out_chi2,
+                         float *out_J, int32_t *out_neff, float *out_grad, float *out_jac,
+                         double *out_cov, const lasp_opts *opts) {
+  g_err.clear();
+  Geometry g;
+  int rc = make_geometry(opts, wave_grid, &g);
   if (rc) return rc;
-  {
-    LASP_TIMED(LASP_K_PREPARE, st);
-    LASP_CHECK(lasp::launch_prepare(g, s, obs, ivar, nullptr, opts->box_lo, opts->box_hi,
-                                    opts->weight_quantile, 0, 0, st),
-               "prepare");
+  if (!obs || !ivar || !basis || !u || !out_chi2)
+    return fail(LASP_E_ARG, "obs, ivar, basis, u and out_chi2 are required");
+  if (g.B == 0) return LASP_OK;
+  hipStream_t st = (hipStream_t)opts->stream;
+  const int rows = (out_jac || out_cov) ? 4 : 1;
+  const int bf16 = opts->precision == LASP_PREC_BF16X3;
+  State s;
+  const size_t need = carve_forward_state(g, rows, bf16, nullptr, &s);
+  if (need > kScratchBytes) {
+    const size_t per = need / (size_t)g.B;
+    char buf[240];
+    snprintf(buf, sizeof buf,
+             "lasp_forward_noalloc: %d spectra of this shape need %zu bytes of scratch; its "
+             "fixed array holds %zu bytes (at most about %zu spectra of this shape)",
+             g.B, need, kScratchBytes, per ? kScratchBytes / per : (size_t)0);
+    return fail(LASP_E_NOMEM, buf);
   }
-  LASP_CHECK(hipMemcpyAsync(s.u, u, sizeof(float) * lasp::kNP * g.B, hipMemcpyDeviceToDevice, st),
-             "copy u");
-  s.fp_stride = rows4 ? 4 * g.ldF : g.ldF;
-  {
-    LASP_TIMED(LASP_K_INTERP_FWD, st);
-    LASP_CHECK(lasp::launch_interp_fwd(g, s, rows4 ? 1 : 0, bf16, st), "interpolator contraction");
-  }
-  {
-    LASP_TIMED(LASP_K_FUSED, st);
-    LASP_CHECK(lasp::launch_fused(g, s, out_grad ? 1 : 0, out_model, 1, st), "fused pass");
-  }
-  if (out_grad) {
-    LASP_TIMED(LASP_K_INTERP_BWD, st);
-    LASP_CHECK(lasp::launch_interp_bwd(g, s, nullptr, out_grad, bf16, st), "adjoint contraction");
-  }
-  if (rows4) {
-    LASP_TIMED(LASP_K_COV, st);
-    LASP_CHECK(lasp::launch_cov(g, s, opts->box_lo, opts->box_hi, out_cov, out_jac, nullptr, nullptr, st),
-               "covariance / model Jacobian");
-  }
-  LASP_CHECK(lasp::launch_outputs(g, s, out_chi2, out_J, out_neff, opts->status, st), "outputs");
-  return LASP_OK;
+  unsigned char *base = nullptr;
+  rc = scratch_address(&base);
+  if (rc) return rc;
+  carve_forward_state(g, rows, bf16, base, &s);
+  // the previous call's contents stay in the array: clear the part this
+  // call uses (a fill kernel, so that a captured call records no memset)
+  hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, reinterpret_cast<uint4 *>(base),
+                     need / 16);
+  LASP_CHECK(hipGetLastError(), "scratch clear");
+  return forward_enqueue(g, s, obs, ivar, basis, u, out_model, out_chi2, out_J, out_neff,
+                         out_grad, out_jac, out_cov, opts);
 }
 
 

@@ -37,7 +37,8 @@ N_PAR = 5
 EXPORTED = ("lasp_default_opts", "lasp_fit_group", "lasp_forward", "lasp_last_error",
             "lasp_release", "lasp_profile_enable", "lasp_profile_read", "lasp_pool_slot_bytes",
             "lasp_pool_create", "lasp_pool_load", "lasp_pool_step", "lasp_pool_progress",
-            "lasp_pool_finish", "lasp_pool_destroy", "lasp_clean_mask", "lasp_resample")
+            "lasp_pool_finish", "lasp_pool_destroy", "lasp_clean_mask", "lasp_resample",
+            "lasp_forward_noalloc")
 KERNELS = ("prepare", "interp_fwd", "fused", "interp_bwd", "cov", "finalize")
 
 
@@ -103,6 +104,8 @@ def load() -> ctypes.CDLL:
         lib.lasp_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                      ctypes.POINTER(LaspOpts)]
         lib.lasp_forward.restype = ctypes.c_int
+        lib.lasp_forward_noalloc.argtypes = lib.lasp_forward.argtypes
+        lib.lasp_forward_noalloc.restype = ctypes.c_int
         lib.lasp_last_error.argtypes = []
         lib.lasp_last_error.restype = ctypes.c_char_p
         lib.lasp_release.argtypes = []
@@ -265,9 +268,11 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
 def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False,
             want_jac=False, want_cov=False, margin=64, degree=10, precision="fp32",
             weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
-            n_classes=1, class_edges=None) -> dict:
+            n_classes=1, class_edges=None, noalloc=False) -> dict:
     """lasp_forward: model, chi2, J, n_eff, gradient, model Jacobian and
-    covariance at fixed normalised u."""
+    covariance at fixed normalised u.  noalloc=True calls
+    lasp_forward_noalloc (the library's fixed scratch array instead of its
+    cached allocations; the result tensors are still allocated here)."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
@@ -290,10 +295,11 @@ def forward(obs, ivar, wave_grid, basis, u, *, want_model=False, want_grad=False
                   n_classes=n_classes, class_edges=class_edges)
     o.status = ctypes.c_void_p(res["status"].data_ptr())
     with torch.cuda.device(dev):
-        rc = lib.lasp_forward(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
-                              _ptr(basis), _ptr(u), _ptr(res["model"]), _ptr(res["chi2"]),
-                              _ptr(res["J"]), _ptr(res["n_eff"]), _ptr(res["grad"]),
-                              _ptr(res["jac"]), _ptr(res["cov"]), ctypes.byref(o))
+        fn = lib.lasp_forward_noalloc if noalloc else lib.lasp_forward
+        rc = fn(_ptr(obs), _ptr(ivar), grid.ctypes.data_as(ctypes.c_void_p),
+                _ptr(basis), _ptr(u), _ptr(res["model"]), _ptr(res["chi2"]),
+                _ptr(res["J"]), _ptr(res["n_eff"]), _ptr(res["grad"]),
+                _ptr(res["jac"]), _ptr(res["cov"]), ctypes.byref(o))
     _check(rc)
     return res
 
