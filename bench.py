@@ -120,27 +120,31 @@ def serving_banks(n_lamost=16384, n_desi=8192):
 
 
 def run_serving(banks, rate, duration, seed=0, n_steps=500, steps_per_tick=25,
-                capacity=(32768, 16384), precision="fp32", size_max=4096, stop_window=0,
-                stop_tol=1e-5):
-    """Serve a seeded Poisson stream of fit requests over one pool per shape.
-    Returns (server, requests done, wall seconds, bank offsets per request)."""
+                precision="fp32", size_max=4096, stop_window=0, stop_tol=1e-5, hbm_budget=0,
+                quantum=1024):
+    """Serve a seeded Poisson stream of fit requests through the library's fit
+    server (one slot pool per shape under one HBM budget).  Returns (server
+    counters at the end, finished requests, wall seconds, bank slice of each
+    request id)."""
     import torch
 
     import paper_2512_24840_amd as lasp
-    from paper_2512_24840_amd.serving import Request, Server
+    from paper_2512_24840_amd.serving import Server
     from synth import poisson_requests, wave_grid
 
     dev = torch.device("cuda:0")
-    dev_banks, pools = {}, {}
-    for (name, (shape, basis, b)), cap in zip(banks.items(), capacity):
+    server = Server(hbm_budget=hbm_budget, n_steps=n_steps, steps_per_tick=steps_per_tick,
+                    capacity_quantum=quantum)
+    dev_banks, sid = {}, {}
+    for name, (shape, basis, b) in banks.items():
         dev_banks[name] = (torch.from_numpy(b.obs).to(dev), torch.from_numpy(b.ivar).to(dev),
                            torch.from_numpy(b.init).to(dev))
         arms = lasp.Arms(shape.arm_start, shape.arm_sigma_kms) if shape.arm_start else None
-        pools[name] = lasp.Pool(wave_grid(shape), torch.from_numpy(basis).to(dev), cap,
-                                margin=shape.margin, degree=shape.degree, arms=arms,
-                                precision=precision, stop_window=stop_window, stop_tol=stop_tol)
+        sid[name] = server.add_shape(wave_grid(shape), torch.from_numpy(basis).to(dev),
+                                     margin=shape.margin, degree=shape.degree, arms=arms,
+                                     precision=precision, stop_window=stop_window,
+                                     stop_tol=stop_tol)
     torch.cuda.synchronize()
-    server = Server(pools, n_steps=n_steps, steps_per_tick=steps_per_tick)
     schedule = poisson_requests(rate, duration, seed, size_max=size_max)
     offsets = {name: 0 for name in banks}
     arrivals, where = [], {}
@@ -150,17 +154,19 @@ def run_serving(banks, rate, duration, seed=0, n_steps=500, steps_per_tick=25,
         offsets[lane] = off + n
         where[rid] = (lane, off, n)
 
-        def make(rid=rid, lane=lane, off=off, n=n, t=t):
+        def make(lane=lane, off=off, n=n):
             o, iv, ini = dev_banks[lane]
-            return Request(rid, lane, o[off:off + n], iv[off:off + n], ini[off:off + n], t)
+            return sid[lane], o[off:off + n], iv[off:off + n], ini[off:off + n]
 
         arrivals.append((t, make))
-    t0 = time.perf_counter()
-    done = server.run(arrivals)
-    wall = time.perf_counter() - t0
-    for p in pools.values():
-        p.close()
-    return server, done, wall, where
+    try:
+        t0 = time.perf_counter()
+        done = server.run(arrivals)      # request ids follow the schedule's order
+        wall = time.perf_counter() - t0
+        stats = server.stats()
+    finally:
+        server.close()
+    return stats, done, wall, where
 
 
 def injection_recovery(params, cov, truth):

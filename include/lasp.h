@@ -353,6 +353,127 @@ int lasp_pool_finish(lasp_pool *pool, int32_t slot0, int32_t count, float *out_p
                      double *out_cov, uint32_t *status, double *chi2);
 int lasp_pool_destroy(lasp_pool *pool);
 
+/*
+ * Pool capacity and footprint.
+ *   lasp_pool_resize    makes the pool hold `capacity` slots, keeping the
+ *                       state of slots [0, keep) (keep <= both capacities);
+ *                       slots past `keep` become idle.  Enqueued on the pool's
+ *                       stream; returns after that stream has finished every
+ *                       earlier step (the old buffers are then freed).
+ *                       LASP_E_NOMEM leaves the pool as it was.
+ *   lasp_pool_bytes     device bytes the pool holds now (capacity x slot
+ *                       bytes + its basis copies).
+ *   lasp_pool_capacity  slots the pool holds now.
+ */
+int lasp_pool_resize(lasp_pool *pool, int32_t capacity, int32_t keep);
+size_t lasp_pool_bytes(const lasp_pool *pool);
+int32_t lasp_pool_capacity(const lasp_pool *pool);
+
+/*
+ * Fit server: continuous batching of fit requests over slot pools under one
+ * device-wide HBM budget (the serving pattern of grouped fitting, Section 2.2
+ * stages 2-9 per request; group sizes as in the paper's Section 4.1 and
+ * Table 2, shapes as in its Section 4.4).
+ *
+ * A server owns one slot pool per spectral shape (lasp_server_add_shape:
+ * pixel grid, basis, arms, continuum degree, precision, Adam settings and
+ * optional stopping rules, as lasp_opts of lasp_pool_create; opts->n_spec
+ * and opts->stream are ignored) and a worker thread on the device that was
+ * current at lasp_server_create.  A request is a group of `count` spectra of
+ * one shape (obs, ivar [count][P], init_params [count][5], device).
+ *  - Admission by HBM footprint: the pools together hold at most
+ *    hbm_budget bytes (lasp_pool_bytes summed over shapes).  A request is
+ *    admitted, in arrival order within its shape, when a contiguous range of
+ *    `count` free slots exists in its shape's pool, or when the pool can grow
+ *    to provide one within the budget; a pool gives capacity back (shrinks to
+ *    its occupied prefix) when another shape's request waits for bytes.
+ *    Pools grow and shrink in multiples of capacity_quantum slots (live
+ *    fits are copied, never restarted).
+ *  - Continuous batching: every tick, each shape with resident fits gets one
+ *    launch sequence of up to steps_per_tick Adam steps covering all of its
+ *    resident fits (per-fit Adam state stays on the device); the shapes run
+ *    on streams of their own and overlap on the device.  A fit's arithmetic
+ *    does not depend on which other fits are resident: a request's results
+ *    are the same alone and in any mix.
+ *  - A request finishes after n_steps Adam steps or, with the shape's
+ *    stopping rules on, once every one of its fits has stopped; it is then
+ *    evaluated (lasp_pool_finish) into the caller's output arrays and
+ *    reported by lasp_server_poll once that work has completed on the
+ *    device.
+ *
+ * lasp_server_default_opts  hbm_budget 0 (= three quarters of the device's
+ *                         free memory at creation), n_steps 500,
+ *                         steps_per_tick 25, want_cov 0,
+ *                         capacity_quantum 1024.
+ * lasp_server_create      starts the server (no shapes yet).
+ * lasp_server_add_shape   adds a shape before the first submit; its id is
+ *                         0, 1, ... in order (at most LASP_SERVER_MAX_SHAPES).
+ *                         LASP_E_NOMEM if its first quantum of slots does not
+ *                         fit the budget.
+ * lasp_server_submit      queues a request.  Inputs and outputs are device
+ *                         arrays owned by the caller that must stay valid
+ *                         until the request is reported done; the inputs
+ *                         must be ready when submit is called (their
+ *                         producing work finished).  Outputs: out_params
+ *                         [count][5] float (physical units, required),
+ *                         out_cov [count][5][5] double (used when want_cov),
+ *                         out_status [count] uint32 (LASP_ST_* bits) and
+ *                         out_chi2 [count] double (either may be NULL).
+ *                         LASP_E_NOMEM if the request could never fit the
+ *                         budget.  *request_id receives its id (0, 1, ...).
+ * lasp_server_poll        moves up to max_done finished requests into
+ *                         done[] (HOST array) and sets *n_done; waits up to
+ *                         timeout_ms for the first one (0: does not wait).
+ *                         Times are seconds on the server's steady clock,
+ *                         from lasp_server_create.
+ * lasp_server_stats       counters and the current footprint (HOST struct).
+ * lasp_server_destroy     stops the worker, waits for the device work it
+ *                         enqueued and frees the pools; requests not yet
+ *                         reported are abandoned (their outputs undefined).
+ * A failure on the worker thread (a HIP error) stops the server: later
+ * submit, poll and stats calls return its code, and lasp_last_error() its
+ * message.  All calls are thread safe.
+ */
+#define LASP_SERVER_MAX_SHAPES 8
+typedef struct lasp_server lasp_server;
+typedef struct lasp_server_opts {
+  size_t hbm_budget;
+  int32_t n_steps;
+  int32_t steps_per_tick;
+  int32_t want_cov;
+  int32_t capacity_quantum;
+} lasp_server_opts;
+typedef struct lasp_request_info {
+  int64_t id;
+  int32_t shape;
+  int32_t count;
+  int32_t max_steps;  /* Adam steps the request's launches covered (each of
+                         its fits took at most this many) */
+  int32_t stopped;    /* 1: finished by the stopping rules before n_steps */
+  double t_submit, t_admit, t_done;
+} lasp_request_info;
+typedef struct lasp_server_counters {
+  size_t hbm_budget;
+  size_t hbm_in_use;  /* bytes the pools hold now */
+  int64_t submitted, completed, ticks, resizes;
+  int32_t queued, active, finishing;
+  int32_t n_shapes;
+  int32_t capacity[LASP_SERVER_MAX_SHAPES];
+  int32_t used_slots[LASP_SERVER_MAX_SHAPES];
+} lasp_server_counters;
+void lasp_server_default_opts(lasp_server_opts *opts);
+int lasp_server_create(const lasp_server_opts *opts, lasp_server **out);
+int lasp_server_add_shape(lasp_server *server, const double *wave_grid, const float *basis,
+                          const lasp_opts *opts, int32_t *shape_id);
+int lasp_server_submit(lasp_server *server, int32_t shape, int32_t count, const float *obs,
+                       const float *ivar, const float *init_params, float *out_params,
+                       double *out_cov, uint32_t *out_status, double *out_chi2,
+                       int64_t *request_id);
+int lasp_server_poll(lasp_server *server, lasp_request_info *done, int32_t max_done,
+                     int32_t timeout_ms, int32_t *n_done);
+int lasp_server_stats(lasp_server *server, lasp_server_counters *stats);
+int lasp_server_destroy(lasp_server *server);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *lasp_last_error(void);
 

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <vector>
 #include <mutex>
@@ -342,13 +343,17 @@ struct ProfRecord {
   int cls;
   hipEvent_t beg, end;
 };
-uint32_t g_prof_mask = 0;
+// Launches may come from several host threads (the server's worker among
+// them): the event lists are guarded by g_prof_mu.
+std::atomic<uint32_t> g_prof_mask{0};
+std::mutex g_prof_mu;
 std::vector<ProfRecord> g_prof;       // recorded, not yet read
 std::vector<hipEvent_t> g_event_pool;  // free events
 double g_prof_ms[LASP_NK];
 int64_t g_prof_n[LASP_NK];
 
 hipEvent_t pool_event() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_event_pool.empty()) {
     hipEvent_t e = g_event_pool.back();
     g_event_pool.pop_back();
@@ -375,11 +380,13 @@ struct ProfScope {
     hipEvent_t end = pool_event();
     if (!end) return;
     (void)hipEventRecord(end, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back(ProfRecord{cls, beg, end});
   }
 };
 
 void prof_drain() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto &r : g_prof) {
     float ms = 0.f;
     if (hipEventSynchronize(r.end) == hipSuccess && hipEventElapsedTime(&ms, r.beg, r.end) == hipSuccess) {
@@ -518,6 +525,10 @@ __global__ void k_zero16(uint4 *p, size_t n) {
 
 }  // namespace
 
+namespace lasp {
+int set_error(int code, const char *msg) { return fail(code, msg ? msg : ""); }
+}  // namespace lasp
+
 extern "C" {
 
 void lasp_default_opts(lasp_opts *o) {
@@ -550,6 +561,7 @@ const char *lasp_last_error(void) { return g_err.c_str(); }
 
 int lasp_profile_enable(uint32_t mask) {
   prof_drain();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   for (int k = 0; k < LASP_NK; ++k) {
     g_prof_ms[k] = 0.0;
     g_prof_n[k] = 0;
@@ -562,6 +574,7 @@ int lasp_profile_read(double *total_ms, int64_t *launches, int32_t n) {
   if (n < 0 || n > LASP_NK || (n > 0 && (!total_ms || !launches)))
     return fail(LASP_E_ARG, "lasp_profile_read: bad arguments");
   prof_drain();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   for (int k = 0; k < n; ++k) {
     total_ms[k] = g_prof_ms[k];
     launches[k] = g_prof_n[k];
@@ -854,6 +867,23 @@ struct lasp_pool {
 };
 
 namespace {
+// Device bytes of one pool slot: the per-spectrum buffers that
+// ensure_buffers allocates for a pool (u, m, v, t, target, rise counter,
+// weight, n_eff, status, d/du4,5, chi2, list entry, loss ring, the
+// (o/w, W w^2) layout, four rows of F' and F-bar').
+size_t slot_bytes_of(const Geometry &g, int stop_window) {
+  return 3 * lasp::kNP * sizeof(float) + 7 * sizeof(int) + 2 * sizeof(float) +
+         sizeof(double) + (size_t)stop_window * sizeof(double) +
+         (size_t)lasp::kNPL * g.block * sizeof(float2) + (size_t)5 * g.ldF * sizeof(float);
+}
+
+// Device bytes of a pool independent of its capacity: the padded basis and
+// its BF16 hi/lo splits (both layouts), and the list length.
+size_t pool_fixed_bytes(const Geometry &g) {
+  return (size_t)g.nb * g.ldF * (sizeof(float) + 2 * sizeof(uint16_t)) +
+         (size_t)2 * 32 * g.ldF * sizeof(uint16_t) + sizeof(int);
+}
+
 int pool_geometry(const lasp_pool *p, int count, Geometry *g) {
   *g = p->g;
   g->B = count;
@@ -866,8 +896,7 @@ extern "C" {
 size_t lasp_pool_slot_bytes(const lasp_opts *opts, const double *wave_grid) {
   Geometry g;
   if (make_geometry(opts, wave_grid, &g)) return 0;
-  return (size_t)lasp::kNPL * g.block * 8 + (size_t)5 * g.ldF * 4 + 64 + 3 * 20 + 52 +
-         (size_t)8 * opts->stop_window;
+  return slot_bytes_of(g, opts->stop_window);
 }
 
 int lasp_pool_create(const double *wave_grid, const float *basis, const lasp_opts *opts,
@@ -996,6 +1025,79 @@ int lasp_pool_finish(lasp_pool *p, int32_t slot0, int32_t count, float *out_para
              "finalize");
   return LASP_OK;
 }
+
+int lasp_pool_resize(lasp_pool *p, int32_t capacity, int32_t keep) {
+  g_err.clear();
+  if (!p) return fail(LASP_E_ARG, "pool is NULL");
+  if (capacity < 1 || keep < 0 || keep > capacity || keep > p->g.B)
+    return fail(LASP_E_ARG, "need capacity >= 1 and 0 <= keep <= min(capacity, current capacity)");
+  if (capacity == p->g.B) return LASP_OK;
+  Geometry g = p->g;
+  g.B = capacity;
+  const int W = p->opts.stop_window;
+  Workspace nw;
+  nw.device = p->device;
+  nw.stream = p->st;
+  int rc = ensure_buffers(&nw, g, 4, W, p->st, false, true);
+  if (rc) return rc;
+  const State &a = p->w.s;
+  const State &b = nw.s;
+  const size_t k = (size_t)keep, ld = (size_t)g.ldF;
+  struct Piece {
+    void *dst;
+    const void *src;
+    size_t bytes;
+  };
+  const Piece pieces[] = {
+      {b.u, a.u, k * lasp::kNP * sizeof(float)},
+      {b.m, a.m, k * lasp::kNP * sizeof(float)},
+      {b.v, a.v, k * lasp::kNP * sizeof(float)},
+      {b.t, a.t, k * sizeof(int)},
+      {b.target, a.target, k * sizeof(int)},
+      {b.nrise, a.nrise, k * sizeof(int)},
+      {b.lhist, a.lhist, W > 0 ? k * W * sizeof(double) : 0},
+      {b.ow, a.ow, k * lasp::kNPL * g.block * sizeof(float2)},
+      {b.wscale, a.wscale, k * sizeof(float)},
+      {b.neff, a.neff, k * sizeof(int)},
+      {b.status, a.status, k * sizeof(uint32_t)},
+      {b.g45, a.g45, k * 2 * sizeof(float)},
+      {b.chi2, a.chi2, k * sizeof(double)},
+      {b.fp, a.fp, k * 4 * ld * sizeof(float)},
+      {b.fbar, a.fbar, k * ld * sizeof(float)},
+      {b.basis, a.basis, (size_t)g.nb * ld * sizeof(float)},
+      {b.basis_hi, a.basis_hi, p->bf16 ? (size_t)g.nb * ld * sizeof(uint16_t) : 0},
+      {b.basis_lo, a.basis_lo, p->bf16 ? (size_t)g.nb * ld * sizeof(uint16_t) : 0},
+      {b.basis_thi, a.basis_thi, p->bf16 ? (size_t)32 * ld * sizeof(uint16_t) : 0},
+      {b.basis_tlo, a.basis_tlo, p->bf16 ? (size_t)32 * ld * sizeof(uint16_t) : 0},
+  };
+  hipError_t e = hipSuccess;
+  for (const Piece &q : pieces)
+    if (e == hipSuccess && q.bytes > 0)
+      e = hipMemcpyAsync(q.dst, q.src, q.bytes, hipMemcpyDeviceToDevice, p->st);
+  // slots past `keep` start idle (step count 0, target 0)
+  if (e == hipSuccess && capacity > keep)
+    e = hipMemsetAsync(b.target + keep, 0, sizeof(int) * (capacity - keep), p->st);
+  if (e == hipSuccess && capacity > keep)
+    e = hipMemsetAsync(b.t + keep, 0, sizeof(int) * (capacity - keep), p->st);
+  // the old buffers are freed only once the copies (and every earlier step
+  // on the pool's stream) have finished
+  if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+  if (e != hipSuccess) {
+    free_ws(&nw);
+    return dev_fail(e, "pool resize");
+  }
+  free_ws(&p->w);
+  p->w = nw;
+  p->g.B = capacity;
+  return LASP_OK;
+}
+
+size_t lasp_pool_bytes(const lasp_pool *p) {
+  if (!p) return 0;
+  return (size_t)p->g.B * slot_bytes_of(p->g, p->opts.stop_window) + pool_fixed_bytes(p->g);
+}
+
+int32_t lasp_pool_capacity(const lasp_pool *p) { return p ? p->g.B : 0; }
 
 int lasp_pool_destroy(lasp_pool *p) {
   if (!p) return LASP_OK;

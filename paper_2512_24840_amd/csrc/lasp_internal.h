@@ -182,6 +182,8 @@ hipError_t launch_resample(const float *src, int n_rows, int n_src, int64_t ld_s
                            double dlam, float *out, int n_out, int64_t ld_out, double lg0,
                            double dlog10, hipStream_t st);
 bool fused_supported(int block, int nd);
+// Sets the calling thread's lasp_last_error() message; returns code.
+int set_error(int code, const char *msg);
 size_t fused_smem_bytes(const Geometry &g);
 
 // -------------------------------------------------------------- device side

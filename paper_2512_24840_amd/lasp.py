@@ -38,7 +38,10 @@ EXPORTED = ("lasp_default_opts", "lasp_fit_group", "lasp_forward", "lasp_last_er
             "lasp_release", "lasp_profile_enable", "lasp_profile_read", "lasp_pool_slot_bytes",
             "lasp_pool_create", "lasp_pool_load", "lasp_pool_step", "lasp_pool_progress",
             "lasp_pool_finish", "lasp_pool_destroy", "lasp_clean_mask", "lasp_resample",
-            "lasp_forward_noalloc")
+            "lasp_forward_noalloc", "lasp_pool_resize", "lasp_pool_bytes", "lasp_pool_capacity",
+            "lasp_server_default_opts", "lasp_server_create", "lasp_server_add_shape",
+            "lasp_server_submit", "lasp_server_poll", "lasp_server_stats", "lasp_server_destroy")
+SERVER_MAX_SHAPES = 8
 KERNELS = ("prepare", "interp_fwd", "fused", "interp_bwd", "cov", "finalize")
 
 
@@ -46,6 +49,28 @@ class LaspError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"{ERRORS.get(code, code)}: {message}")
         self.code = code
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("n_steps", ctypes.c_int32),
+                ("steps_per_tick", ctypes.c_int32), ("want_cov", ctypes.c_int32),
+                ("capacity_quantum", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("shape", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("stopped", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("hbm_in_use", ctypes.c_size_t),
+                ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("resizes", ctypes.c_int64),
+                ("queued", ctypes.c_int32), ("active", ctypes.c_int32),
+                ("finishing", ctypes.c_int32), ("n_shapes", ctypes.c_int32),
+                ("capacity", ctypes.c_int32 * 8), ("used_slots", ctypes.c_int32 * 8)]
 
 
 class LaspOpts(ctypes.Structure):
@@ -138,6 +163,29 @@ def load() -> ctypes.CDLL:
         lib.lasp_resample.restype = ctypes.c_int
         lib.lasp_pool_destroy.argtypes = [vp]
         lib.lasp_pool_destroy.restype = ctypes.c_int
+        lib.lasp_pool_resize.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        lib.lasp_pool_resize.restype = ctypes.c_int
+        lib.lasp_pool_bytes.argtypes = [vp]
+        lib.lasp_pool_bytes.restype = ctypes.c_size_t
+        lib.lasp_pool_capacity.argtypes = [vp]
+        lib.lasp_pool_capacity.restype = ctypes.c_int32
+        lib.lasp_server_default_opts.argtypes = [ctypes.POINTER(ServerOpts)]
+        lib.lasp_server_default_opts.restype = None
+        lib.lasp_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        lib.lasp_server_create.restype = ctypes.c_int
+        lib.lasp_server_add_shape.argtypes = [vp, vp, vp, ctypes.POINTER(LaspOpts),
+                                              ctypes.POINTER(ctypes.c_int32)]
+        lib.lasp_server_add_shape.restype = ctypes.c_int
+        lib.lasp_server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
+                                           vp, vp, ctypes.POINTER(ctypes.c_int64)]
+        lib.lasp_server_submit.restype = ctypes.c_int
+        lib.lasp_server_poll.argtypes = [vp, ctypes.POINTER(RequestInfo), ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        lib.lasp_server_poll.restype = ctypes.c_int
+        lib.lasp_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
+        lib.lasp_server_stats.restype = ctypes.c_int
+        lib.lasp_server_destroy.argtypes = [vp]
+        lib.lasp_server_destroy.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -420,6 +468,15 @@ class Pool:
         _dev(params, "params", torch.float32, (n, N_PAR))
         _check(load().lasp_pool_finish(self._p, int(slot0), int(n), _ptr(params), _ptr(cov),
                                        _ptr(status), _ptr(chi2)))
+
+    def resize(self, capacity, keep):
+        """lasp_pool_resize: hold `capacity` slots, keeping slots [0, keep)."""
+        _check(load().lasp_pool_resize(self._p, int(capacity), int(keep)))
+        self.capacity = int(load().lasp_pool_capacity(self._p))
+
+    @property
+    def bytes(self) -> int:
+        return int(load().lasp_pool_bytes(self._p))
 
     def close(self):
         if self._p:

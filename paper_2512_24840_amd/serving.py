@@ -1,244 +1,194 @@
-"""Continuous batching of fit requests over device-resident slot pools.
+"""Binding of the library's fit server (lasp_server_*): argument marshalling
+and request bookkeeping only.
 
-Each spectral shape (pixel count, grid, basis, arms) has a ``Pool`` of fit
-slots on its own HIP stream.  A request (a group of spectra of one shape) is
-admitted when its memory footprint (spectra x bytes per slot) fits in a
-contiguous free slot range, loaded into those slots (per-slot Adam state
-starts at step 0), and then advances together with every other resident fit
-each tick (k Adam steps per tick, one launch sequence per shape, the shapes'
-streams overlapping on the device).  When a request has taken its n_steps,
-its slots are evaluated, the results are copied to pinned host memory and,
-once that copy has completed, the slots are freed for queued requests.  With
-the stopping rules on (a pool created with stop_window > 0) a request also
-finishes as soon as every one of its fits has stopped: each tick enqueues a
-copy of the pool's per-slot stopped flags to pinned memory and a later tick
-reads it.
-
-All arithmetic runs in the library's kernels; this module is bookkeeping:
-slot allocation, queues, tick pacing and latency timestamps.
+The server itself is native (csrc/lasp_server.hip): a worker thread admits
+requests by HBM footprint against one device-wide budget, grows and shrinks
+one slot pool per spectral shape inside that budget, advances every
+resident fit of a shape with one launch sequence per tick (the shapes on
+streams of their own, overlapping on the device), and evaluates finished
+requests into the caller's output tensors.  This module allocates those
+output tensors, keeps each request's tensors alive until the server reports
+it done, and converts the server's timestamps into latencies.
 """
 
 from __future__ import annotations
 
-import bisect
+import ctypes
 import dataclasses
 import time
-from collections import deque
 
+import numpy as np
 import torch
 
-from .lasp import N_PAR, Pool
-
-
-class SlotAllocator:
-    """First-fit allocator of contiguous slot ranges in [0, capacity)."""
-
-    def __init__(self, capacity: int):
-        self.capacity = capacity
-        self.free = [(0, capacity)]          # sorted, disjoint (start, length)
-        self.used = {}                       # start -> length
-
-    def alloc(self, n: int):
-        for i, (s, l) in enumerate(self.free):
-            if l >= n:
-                if l == n:
-                    self.free.pop(i)
-                else:
-                    self.free[i] = (s + n, l - n)
-                self.used[s] = n
-                return s
-        return None
-
-    def release(self, start: int):
-        n = self.used.pop(start)
-        i = bisect.bisect_left(self.free, (start, 0))
-        self.free.insert(i, (start, n))
-        merged = []
-        for s, l in self.free:
-            if merged and merged[-1][0] + merged[-1][1] == s:
-                merged[-1] = (merged[-1][0], merged[-1][1] + l)
-            else:
-                merged.append((s, l))
-        self.free = merged
-
-    def high_water(self) -> int:
-        return max((s + l for s, l in self.used.items()), default=0)
-
-    def used_slots(self) -> int:
-        return sum(self.used.values())
+from .lasp import (N_BASIS, N_PAR, Arms, RequestInfo, ServerCounters, ServerOpts, _check, _dev,
+                   _grid, _ptr, load, make_opts)
 
 
 @dataclasses.dataclass
 class Request:
     rid: int
-    lane: str
-    obs: torch.Tensor          # [n, P] device
+    shape: int
+    obs: torch.Tensor              # [n, P] device (kept alive until done)
     ivar: torch.Tensor
-    init: torch.Tensor         # [n, 5] device
-    t_arrival: float
-    slot0: int = -1
-    steps: int = 0
-    t_admit: float = 0.0
-    t_done: float = 0.0
-    admit_tick: int = -1
-    params: torch.Tensor | None = None   # pinned host results
-    status: torch.Tensor | None = None
-    chi2: torch.Tensor | None = None
+    init: torch.Tensor             # [n, 5] device
+    params: torch.Tensor           # [n, 5] float32 device output
+    status: torch.Tensor           # [n] int32 device output
+    chi2: torch.Tensor             # [n] float64 device output
     cov: torch.Tensor | None = None
-    event: torch.cuda.Event | None = None
+    t_arrival: float | None = None  # scheduled arrival, server clock (s)
+    info: RequestInfo | None = None
 
     @property
     def n(self) -> int:
         return self.obs.shape[0]
 
-
-class Lane:
-    """One shape: its pool, allocator, queue and resident requests."""
-
-    def __init__(self, name: str, pool: Pool):
-        self.name = name
-        self.pool = pool
-        self.alloc = SlotAllocator(pool.capacity)
-        self.queue: deque[Request] = deque()
-        self.active: list[Request] = []
-        self.finishing: list[Request] = []
-        self.tick_event: torch.cuda.Event | None = None
-        # stopped flags of the slots (stopping rules): device copy, pinned
-        # host copy, the event that marks the host copy complete and the
-        # tick at which the flags were taken
-        self.done_dev = self.done_host = self.snap_event = None
-        self.snap_tick = -1
-        if pool.stop_window > 0:
-            self.done_dev = torch.zeros(pool.capacity, dtype=torch.int32, device=pool.device)
-            self.done_host = torch.zeros(pool.capacity, dtype=torch.int32, pin_memory=True)
-
     @property
-    def footprint_bytes(self) -> int:
-        return self.alloc.used_slots() * self.pool.slot_bytes
+    def latency_s(self) -> float:
+        """Arrival (or submit) to results complete in device memory."""
+        t0 = self.info.t_submit if self.t_arrival is None else min(self.t_arrival,
+                                                                  self.info.t_submit)
+        return self.info.t_done - t0
 
 
 class Server:
-    def __init__(self, lanes: dict[str, Pool], n_steps: int = 500, steps_per_tick: int = 25,
-                 want_cov: bool = False):
-        self.lanes = {k: Lane(k, p) for k, p in lanes.items()}
-        self.n_steps = n_steps
-        self.k = steps_per_tick
-        self.want_cov = want_cov
-        self.done: list[Request] = []
-        self.ticks = 0
+    """lasp_server_* on the current device."""
 
-    def submit(self, req: Request):
-        self.lanes[req.lane].queue.append(req)
+    def __init__(self, *, hbm_budget: int = 0, n_steps: int = 500, steps_per_tick: int = 25,
+                 want_cov: bool = False, capacity_quantum: int = 1024, device=None):
+        lib = load()
+        o = ServerOpts()
+        lib.lasp_server_default_opts(ctypes.byref(o))
+        o.hbm_budget = int(hbm_budget)
+        o.n_steps, o.steps_per_tick = int(n_steps), int(steps_per_tick)
+        o.want_cov, o.capacity_quantum = int(bool(want_cov)), int(capacity_quantum)
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self.want_cov = bool(want_cov)
+        self.n_steps = int(n_steps)
+        self._s = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.lasp_server_create(ctypes.byref(o), ctypes.byref(self._s)))
+        self._t0 = time.perf_counter()        # the server clock's origin, this process's clock
+        self._pending: dict[int, Request] = {}
+        self._shapes: list[int] = []           # pixels per shape
+        self._keep = []                        # host grids of the shapes
 
-    def _admit(self, lane: Lane, now: float):
-        while lane.queue:
-            req = lane.queue[0]
-            if req.n > lane.pool.capacity:
-                raise ValueError(f"request of {req.n} spectra exceeds the pool capacity")
-            slot0 = lane.alloc.alloc(req.n)
-            if slot0 is None:
-                return                         # wait for memory to free up
-            lane.queue.popleft()
-            req.slot0 = slot0
-            req.t_admit = now
-            req.admit_tick = self.ticks
-            with torch.cuda.stream(lane.pool.stream):
-                lane.pool.load(slot0, req.obs, req.ivar, req.init, self.n_steps)
-            lane.active.append(req)
+    def clock(self) -> float:
+        """Seconds on the server's clock (approximately)."""
+        return time.perf_counter() - self._t0
 
-    def _finish(self, lane: Lane, req: Request):
-        dev = lane.pool.device
-        n = req.n
-        with torch.cuda.stream(lane.pool.stream):
-            p = torch.empty((n, N_PAR), dtype=torch.float32, device=dev)
-            st = torch.empty(n, dtype=torch.int32, device=dev)
-            c2 = torch.empty(n, dtype=torch.float64, device=dev)
-            cv = (torch.empty((n, N_PAR, N_PAR), dtype=torch.float64, device=dev)
-                  if self.want_cov else None)
-            lane.pool.finish(req.slot0, p, cv, st, c2)
-            req.params = torch.empty((n, N_PAR), dtype=torch.float32, pin_memory=True)
-            req.status = torch.empty(n, dtype=torch.int32, pin_memory=True)
-            req.chi2 = torch.empty(n, dtype=torch.float64, pin_memory=True)
-            req.params.copy_(p, non_blocking=True)
-            req.status.copy_(st, non_blocking=True)
-            req.chi2.copy_(c2, non_blocking=True)
-            if cv is not None:
-                req.cov = torch.empty((n, N_PAR, N_PAR), dtype=torch.float64, pin_memory=True)
-                req.cov.copy_(cv, non_blocking=True)
-            req.event = torch.cuda.Event()
-            req.event.record(lane.pool.stream)
-        lane.finishing.append(req)
+    def add_shape(self, wave_grid, basis, *, margin=64, degree=10, precision="fp32", lr=1e-2,
+                  betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5, arms: Arms | None = None,
+                  box=None, stop_window=0, stop_tol=1e-5, n_classes=1, class_edges=None) -> int:
+        P = int(np.asarray(wave_grid).shape[0])
+        _dev(basis, "basis", torch.float32, (N_BASIS * n_classes, P + 2 * margin))
+        grid = _grid(wave_grid, P)
+        opts = make_opts(1, P, margin=margin, degree=degree, precision=precision, lr=lr,
+                         betas=betas, eps=eps, weight_quantile=weight_quantile, arms=arms,
+                         box=box, stream=torch.cuda.current_stream(self.device),
+                         stop_window=stop_window, stop_tol=stop_tol, n_classes=n_classes,
+                         class_edges=class_edges)
+        sid = ctypes.c_int32()
+        torch.cuda.current_stream(self.device).synchronize()   # basis ready
+        with torch.cuda.device(self.device):
+            _check(load().lasp_server_add_shape(self._s, grid.ctypes.data_as(ctypes.c_void_p),
+                                                _ptr(basis), ctypes.byref(opts),
+                                                ctypes.byref(sid)))
+        self._shapes.append(P)
+        self._keep.append(grid)
+        return int(sid.value)
 
-    def tick(self, now: float):
-        """Admit, advance every resident fit by k steps, start finished ones."""
-        for lane in self.lanes.values():
-            self._admit(lane, now)
-        for lane in self.lanes.values():
-            if not lane.active:
-                continue
-            prev = lane.tick_event
-            with torch.cuda.stream(lane.pool.stream):
-                k = min(self.k, max(self.n_steps - r.steps for r in lane.active))
-                lane.pool.step(lane.alloc.high_water(), k)
-                for r in lane.active:
-                    r.steps += k
-                fin = [r for r in lane.active if r.steps >= self.n_steps]
-                if lane.snap_event is not None and lane.snap_event.query():
-                    flags = lane.done_host.numpy()
-                    for r in lane.active:
-                        # flags taken before r was loaded belong to older fits
-                        if (r not in fin and r.admit_tick <= lane.snap_tick
-                                and flags[r.slot0:r.slot0 + r.n].all()):
-                            fin.append(r)
-                    lane.snap_event = None
-                for r in fin:
-                    lane.active.remove(r)
-                    self._finish(lane, r)
-                if lane.done_dev is not None and lane.snap_event is None and lane.active:
-                    hw = lane.alloc.high_water()
-                    lane.pool.progress(0, done=lane.done_dev[:hw])
-                    lane.done_host[:hw].copy_(lane.done_dev[:hw], non_blocking=True)
-                    lane.snap_event = torch.cuda.Event()
-                    lane.snap_event.record(lane.pool.stream)
-                    lane.snap_tick = self.ticks
-                lane.tick_event = torch.cuda.Event()
-                lane.tick_event.record(lane.pool.stream)
-            if prev is not None:
-                prev.synchronize()             # keep at most two ticks in flight
-        self.ticks += 1
+    def submit(self, shape: int, obs, ivar, init_params, t_arrival: float | None = None) -> Request:
+        """Queue a group of spectra (device tensors whose producing work has
+        finished).  t_arrival: scheduled arrival on the server clock, for the
+        latency (defaults to the submit time)."""
+        n, P = obs.shape
+        if shape < 0 or shape >= len(self._shapes) or P != self._shapes[shape]:
+            raise ValueError("obs does not match the shape's pixel count")
+        _dev(obs, "obs", torch.float32, (n, P))
+        _dev(ivar, "ivar", torch.float32, (n, P))
+        _dev(init_params, "init_params", torch.float32, (n, N_PAR))
+        dev = obs.device
+        req = Request(-1, shape, obs, ivar, init_params,
+                      torch.empty((n, N_PAR), dtype=torch.float32, device=dev),
+                      torch.empty(n, dtype=torch.int32, device=dev),
+                      torch.empty(n, dtype=torch.float64, device=dev),
+                      torch.empty((n, N_PAR, N_PAR), dtype=torch.float64, device=dev)
+                      if self.want_cov else None, t_arrival)
+        # the server's stream must not overtake work on this stream that
+        # produced the inputs or last used the outputs' memory
+        torch.cuda.current_stream(dev).synchronize()
+        rid = ctypes.c_int64()
+        _check(load().lasp_server_submit(self._s, int(shape), int(n), _ptr(obs), _ptr(ivar),
+                                         _ptr(init_params), _ptr(req.params), _ptr(req.cov),
+                                         _ptr(req.status), _ptr(req.chi2), ctypes.byref(rid)))
+        req.rid = int(rid.value)
+        self._pending[req.rid] = req
+        return req
 
-    def poll(self, now: float) -> int:
-        """Collect finished requests whose results reached the host."""
-        n = 0
-        for lane in self.lanes.values():
-            for r in list(lane.finishing):
-                if r.event.query():
-                    r.t_done = now
-                    lane.finishing.remove(r)
-                    lane.alloc.release(r.slot0)
-                    self.done.append(r)
-                    n += 1
-        return n
+    def poll(self, timeout_ms: int = 0, max_done: int = 256) -> list[Request]:
+        """Requests finished since the last poll (their outputs are complete)."""
+        buf = (RequestInfo * max_done)()
+        n = ctypes.c_int32()
+        _check(load().lasp_server_poll(self._s, buf, int(max_done), int(timeout_ms),
+                                       ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            info = RequestInfo.from_buffer_copy(buf[i])
+            req = self._pending.pop(int(info.id))
+            req.info = info
+            out.append(req)
+        return out
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(load().lasp_server_stats(self._s, ctypes.byref(c)))
+        d = {f: getattr(c, f) for f, _ in ServerCounters._fields_}
+        d["capacity"] = list(c.capacity)[:c.n_shapes]
+        d["used_slots"] = list(c.used_slots)[:c.n_shapes]
+        return d
 
     def busy(self) -> bool:
-        return any(l.queue or l.active or l.finishing for l in self.lanes.values())
+        return bool(self._pending)
 
-    def run(self, arrivals, clock=time.perf_counter, t_end: float | None = None):
-        """Serve ``arrivals`` (sorted list of (t_offset, Request factory))."""
-        t0 = clock()
+    def run(self, arrivals, t_end: float | None = None, stall_s: float = 60.0) -> list[Request]:
+        """Serve a schedule: ``arrivals`` is a sorted list of (offset s,
+        factory) where factory() returns (shape, obs, ivar, init).  Each
+        request is submitted once its offset has passed on the server clock
+        (counted from this call) and carries that offset as its arrival.
+        Returns the finished requests; raises if nothing finishes for
+        stall_s seconds while requests are pending."""
+        done = []
+        start = self.clock()
+        last = start
         i = 0
-        while i < len(arrivals) or self.busy():
-            now = clock() - t0
+        while i < len(arrivals) or self._pending:
+            now = self.clock() - start
+            if self._pending and self.clock() - last > stall_s:
+                raise RuntimeError(f"no request finished in {stall_s} s: {self.stats()}")
             while i < len(arrivals) and arrivals[i][0] <= now:
-                req = arrivals[i][1]()
-                req.t_arrival = t0 + arrivals[i][0]
-                self.submit(req)
+                shape, obs, ivar, init = arrivals[i][1]()
+                self.submit(shape, obs, ivar, init, t_arrival=start + arrivals[i][0])
                 i += 1
-            if any(l.queue or l.active for l in self.lanes.values()):
-                self.tick(clock())
-            elif i < len(arrivals):
-                time.sleep(min(0.002, max(0.0, arrivals[i][0] - now)))
-            self.poll(clock())
+            wait = 2
+            if i < len(arrivals):
+                wait = int(max(0.0, min(0.002, arrivals[i][0] - now)) * 1e3)
+            got = self.poll(timeout_ms=wait)
+            if got:
+                last = self.clock()
+                done.extend(got)
             if t_end is not None and now > t_end:
                 break
-        return self.done
+        return done
+
+    def close(self):
+        if self._s:
+            load().lasp_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
