@@ -183,7 +183,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   for (int i = 0; i < kNPL; ++i) fpp[i] = 0.f;
   if (has_pix) {
     for (int a = wa_lo; a <= wa_hi; ++a) {
-      const int H = sHa[a], T = 2 * H + 1;
+      const int H = __builtin_amdgcn_readfirstlane(sHa[a]), T = 2 * H + 1;
       const float *K = sK + a * L.ks;
       float acc[kNPL];
 #pragma unroll
@@ -213,88 +213,73 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     }
   }
 
-  // ---- Eq. 6 moments: nu_l = sum W F''^2 T_l, r_n = sum W F'' o T_n.  Each
-  //      lane sums its 17 pixels in FP32; the sums over lanes and waves, and
-  //      the solve, are FP64.  Two passes (nu, then r): fewer live values.
+  // ---- Eq. 6 moments: nu_l = sum W F''^2 T_l (l <= 2D), r_n = sum W F'' o T_n
+  //      (n <= D), in one pass over the lane's pixels with T_0 .. T_D only:
+  //      T_{D+k} = 2 T_D T_k - T_{D-k}, so nu_{D+k} = 2 q_k - nu_{D-k} with
+  //      q_k = sum W F''^2 T_D T_k (k = 1..D).  Each lane sums its 17 pixels
+  //      in FP32; the sums over lanes and waves, the combination and the
+  //      solve are FP64.
   {
     double *scr = reinterpret_cast<double *>(sF + L.gb_off);
     const float two_over_p = 2.f / (float)P;
-    {
+    const float x0 = fmaf((float)j0, two_over_p, -1.f);
 #pragma unroll
-      for (int i = 0; i < kNPL; ++i) {
-        opaque(fpp[i]);
-        opaque(ow[i]);
-      }
-      float nu[NNU];
-#pragma unroll
-      for (int k = 0; k < NNU; ++k) nu[k] = 0.f;
-#pragma unroll
-      for (int i = 0; i < kNPL; ++i) {
-        const float x = fmaf((float)(j0 + i), two_over_p, -1.f);
-        const float y = ow[i].y * fpp[i] * fpp[i];
-        float tm = 1.f, tc = x;
-        nu[0] += y;
-        nu[1] = fmaf(y, x, nu[1]);
-        const float x2 = x + x;
-#pragma unroll
-        for (int l = 2; l < NNU; ++l) {
-          const float tn = fmaf(x2, tc, -tm);
-          nu[l] = fmaf(y, tn, nu[l]);
-          tm = tc;
-          tc = tn;
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      double acc[NNU];
-#pragma unroll
-      for (int k = 0; k < NNU; ++k) acc[k] = (double)nu[k];
-      block_sum_lds<NW, NNU>(acc, scr, sRed, sMom, lane, wave);
+    for (int i = 0; i < kNPL; ++i) {
+      opaque(fpp[i]);
+      opaque(ow[i]);
     }
-    {
+    float nu[ND], q[ND], rr[ND];  // nu_0..nu_D, q_1..q_D (q[0] unused), r_0..r_D
 #pragma unroll
-      for (int i = 0; i < kNPL; ++i) {
-        opaque(fpp[i]);
-        opaque(ow[i]);
+    for (int k = 0; k < ND; ++k) nu[k] = q[k] = rr[k] = 0.f;
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i) {
+      const float x = fmaf((float)i, two_over_p, x0);
+      const float wf = ow[i].y * fpp[i];
+      const float y = wf * fpp[i];   // W F''^2
+      const float z = wf * ow[i].x;  // W F'' o
+      const float x2 = x + x;
+      float t[ND];  // T_0(x) .. T_D(x)
+      t[0] = 1.f;
+      t[1] = x;
+#pragma unroll
+      for (int l = 2; l < ND; ++l) t[l] = fmaf(x2, t[l - 1], -t[l - 2]);
+      const float yd = y * t[ND - 1];
+      nu[0] += y;
+      rr[0] += z;
+#pragma unroll
+      for (int l = 1; l < ND; ++l) {
+        nu[l] = fmaf(y, t[l], nu[l]);
+        q[l] = fmaf(yd, t[l], q[l]);
+        rr[l] = fmaf(z, t[l], rr[l]);
       }
-      int jb = j0;
-      opaque(jb);
-      float rr[ND];
-#pragma unroll
-      for (int k = 0; k < ND; ++k) rr[k] = 0.f;
-#pragma unroll
-      for (int i = 0; i < kNPL; ++i) {
-        const float x = fmaf((float)(jb + i), two_over_p, -1.f);
-        const float z = ow[i].y * fpp[i] * ow[i].x;
-        float tm = 1.f, tc = x;
-        rr[0] += z;
-        rr[1] = fmaf(z, x, rr[1]);
-        const float x2 = x + x;
-#pragma unroll
-        for (int l = 2; l < ND; ++l) {
-          const float tn = fmaf(x2, tc, -tm);
-          rr[l] = fmaf(z, tn, rr[l]);
-          tm = tc;
-          tc = tn;
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      double acc[ND];
-#pragma unroll
-      for (int k = 0; k < ND; ++k) acc[k] = (double)rr[k];
-      block_sum_lds<NW, ND>(acc, scr, sRed, sMom + NNU, lane, wave);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
+    // lane partials in the order nu_0..nu_D, q_1..q_D, r_0..r_D
+    float acc[NMOM];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = nu[k];
+#pragma unroll
+    for (int k = 1; k < ND; ++k) acc[ND - 1 + k] = q[k];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[NNU + k] = rr[k];
+    block_sum_lds<NW, NMOM>(acc, scr, sRed, sMom, lane, wave);
+    for (int q2 = tid; q2 < L.gb_len; q2 += BLOCK) sF[L.gb_off + q2] = 0.f;
   }
 
   // ---- normal equations A b = r (A_mn = (nu_{m+n} + nu_|m-n|)/2), solved
-  //      in FP64 by Gauss-Jordan elimination, lane i holding row i --------
+  //      in FP64 by Gauss-Jordan elimination, lane i holding row i.  sMom
+  //      holds nu_0..nu_D, then q_1..q_D with nu_{D+k} = 2 q_k - nu_{D-k}.
   if (wave == 0) {
+    constexpr int D = ND - 1;
+    auto nu_at = [&](int l) {
+      return l <= D ? sMom[l] : 2.0 * sMom[l] - sMom[2 * D - l];
+    };
     double a[ND + 1];
     const bool row = lane < ND;
 #pragma unroll
     for (int n = 0; n < ND; ++n) {
       const int d = lane > n ? lane - n : n - lane;
-      a[n] = row ? 0.5 * (sMom[min(lane + n, NNU - 1)] + sMom[min(d, NNU - 1)]) : 0.0;
+      a[n] = row ? 0.5 * (nu_at(min(lane + n, NNU - 1)) + nu_at(min(d, NNU - 1))) : 0.0;
     }
     a[ND] = row ? sMom[NNU + min(lane, ND - 1)] : 0.0;
     bool ok = true;
@@ -395,7 +380,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   // ---- lag correlation R_a(m) = sum_{j in arm a} g_j F'_{j-m+M} ----------
   if (wp0 < P) {
     for (int a = wa_lo; a <= wa_hi; ++a) {
-      const int H = sHa[a], T = 2 * H + 1;
+      const int H = __builtin_amdgcn_readfirstlane(sHa[a]), T = 2 * H + 1;
       float gm[kNPL];
       if constexpr (!multi) {
 #pragma unroll
@@ -455,7 +440,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   if (wave == 0) {
     double g4 = 0.0, g5 = 0.0;
     for (int a = 0; a < g.n_arms; ++a) {
-      const int H = sHa[a], T = 2 * H + 1;
+      const int H = __builtin_amdgcn_readfirstlane(sHa[a]), T = 2 * H + 1;
       double s1 = 0, s2 = 0, rg = 0, rgd = 0, rgd2 = 0;
       for (int idx = lane; idx < T; idx += 64) {
         const double d = (double)(idx - H) - mu;
@@ -510,7 +495,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       }
     }
     for (int a = ta_lo; a <= ta_hi; ++a) {
-      const int H = sHa[a], T = 2 * H + 1;
+      const int H = __builtin_amdgcn_readfirstlane(sHa[a]), T = 2 * H + 1;
       const float *K = sK + a * L.ks;
       const int lo = multi ? g.arm_start[a] : 0;
       const int hi = multi ? g.arm_start[a + 1] : P;

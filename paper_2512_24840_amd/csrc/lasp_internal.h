@@ -410,15 +410,17 @@ __device__ inline void wave_sum_lds(const double (&acc)[NV], double *scratch, do
 // 4 KB), each group of eight lanes adds one value's 64 partials, then the
 // waves' results are added in a fixed order.  out[0..NV) is valid for every
 // thread after the call.  Deterministic.
-template <int NW, int NV>
-__device__ inline void block_sum_lds(const double (&acc)[NV], double *scratch, double *red,
+template <int NW, int NV, typename T>
+__device__ inline void block_sum_lds(const T (&acc)[NV], double *scratch, double *red,
                                      double *out, int lane, int wave) {
   double *sc = scratch + wave * 512;
   const int tt = lane >> 3, part = lane & 7;
 #pragma unroll
   for (int c = 0; c < (NV + 7) / 8; ++c) {
+    // FP32 partials are widened 8 at a time, so few doubles are live at once
 #pragma unroll
-    for (int t = 0; t < 8; ++t) sc[t * 64 + lane] = (8 * c + t < NV) ? acc[(8 * c + t) % NV] : 0.0;
+    for (int t = 0; t < 8; ++t)
+      sc[t * 64 + lane] = (8 * c + t < NV) ? (double)acc[(8 * c + t) % NV] : 0.0;
     wave_lds_sync();
     const double *row = sc + tt * 64 + 8 * part;
     double v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));

@@ -69,7 +69,7 @@ def test_poisson_stream_alone_equals_mix_and_matches_oracle():
     for lane in ("lamost3900", "desi7800"):
         mine = sorted((r for r in done if where[r.rid][0] == lane), key=lambda r: -r.n)[:16]
         for r in mine:
-            _, off, n = where[r.rid]
+            _, off, n, _ = where[r.rid]
             shape, basis, b = banks[lane]
             a = alone(shape, basis, b, off, n)
             assert np.array_equal(a.params.cpu().numpy(), r.params.cpu().numpy()), (lane, r.rid)
@@ -79,7 +79,7 @@ def test_poisson_stream_alone_equals_mix_and_matches_oracle():
     for r in done:
         if r.rid % 8:
             continue
-        lane, off, n = where[r.rid]
+        lane, off, n, _ = where[r.rid]
         shape, basis, b = banks[lane]
         err = check_oracle(shape, basis, b, off, r.params[0].cpu().numpy())
         n_chk += 1
@@ -100,7 +100,7 @@ def test_stream_with_stopping_rules_releases_requests_early_and_matches_grouped_
     for r in early:
         assert r.info.max_steps < 500
     for r in sorted(done, key=lambda r: -r.n)[:4]:
-        lane, off, n = where[r.rid]
+        lane, off, n, _ = where[r.rid]
         shape, basis, b = banks[lane]
         a = alone(shape, basis, b, off, n, stop_window=50, stop_tol=1e-5)
         assert np.array_equal(a.params.cpu().numpy(), r.params.cpu().numpy()), (lane, r.rid)
