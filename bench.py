@@ -20,8 +20,9 @@ with its own timing and oracle check:
                   every fitted parameter
   autograd_65536  65,536 x 3,900 px forward + adjoint through the
                   torch.autograd.Function, then the covariance
-  serving         a Poisson stream of fit requests through the library's fit
-                  server (60 s measured after 5 s of warm-up)
+  serving         Poisson streams of fit requests through the library's fit
+                  server: 20k spectra/s with the stopping rules (60 s measured
+                  after 5 s of warm-up), and 500 fixed steps at 10k spectra/s
 plus the stopping rules, Clean, Levenberg-Marquardt, three-class emulator,
 resampling and group-size legs.
 """
@@ -90,6 +91,10 @@ def parse(argv=None):
                    help="grouped run: measured seconds of the served stream leg")
     p.add_argument("--serving-warmup", type=float, default=5.0,
                    help="seconds of the served stream before the measured window")
+    p.add_argument("--serving-fixed-rate", type=float, default=10000.0,
+                   help="offered spectra/s of the fixed-step served stream leg")
+    p.add_argument("--serving-fixed-seconds", type=float, default=20.0,
+                   help="measured seconds of the fixed-step served stream leg")
     p.add_argument("--emulator-oracle-sample", type=int, default=48,
                    help="emulator leg: spectra checked against the oracle's 3-class fit")
     p.add_argument("--large-spectra", type=int, default=262144,
@@ -259,7 +264,8 @@ def injection_recovery(params, cov, truth):
             "pull_std": {k: float(pull[:, i].std()) for i, k in enumerate(names)}}
 
 
-def alone_equals_mix(banks, meas, where, precision, n_per_shape=16):
+def alone_equals_mix(banks, meas, where, precision, n_per_shape=16, stop_window=0,
+                     stop_tol=1e-5):
     """Bitwise comparison of served results with the same spectra fitted alone
     in one grouped fit, for the largest n_per_shape requests of each shape."""
     import torch
@@ -280,7 +286,8 @@ def alone_equals_mix(banks, meas, where, precision, n_per_shape=16):
                                torch.from_numpy(basis).to(dev),
                                torch.from_numpy(b.init[off:off + n]).to(dev), 500,
                                margin=shape.margin, degree=shape.degree, arms=arms,
-                               precision=precision)
+                               precision=precision, stop_window=stop_window,
+                               stop_tol=stop_tol)
             torch.cuda.synchronize()
             checked += 1
             same += int(np.array_equal(a.params.cpu().numpy(), r.params.cpu().numpy())
@@ -288,22 +295,38 @@ def alone_equals_mix(banks, meas, where, precision, n_per_shape=16):
     return {"n": checked, "bitwise_equal": same}
 
 
-def serving_oracle(banks, meas, where, every=64):
+def serving_oracle(banks, meas, where, every=64, window=0, tol=1e-5):
+    """First spectrum of every `every`-th request against the oracle's LM fit
+    (fitted-value tolerances) and, with the stopping rules on, against the
+    oracle's FP64 Adam under the same rules (the like-for-like fit)."""
     import oracle
     from synth import BOX_HI, BOX_LO
 
-    ok = n = 0
+    threads = os.cpu_count() or 1
+    picks = {}
     for r in meas:
-        if r.rid % every:
-            continue
-        lane, off, cnt, _ = where[r.rid]
+        if r.rid % every == 0:
+            lane, off, _, _ = where[r.rid]
+            picks.setdefault(lane, []).append((off, r.params[0].cpu().numpy().astype(np.float64)))
+    ok = ok_a = n = 0
+    for lane, items in picks.items():
         shape, basis, b = banks[lane]
         cfg = oracle.Config.from_shape(shape, BOX_LO, BOX_HI)
-        ref = oracle.fit(cfg, b.obs[off], b.ivar[off], basis, cfg.normalise(b.init[off]))
-        err = np.abs(r.params[0].cpu().numpy().astype(np.float64) - ref["params"])[:4]
-        ok += int(np.all(err <= FIT_TOL))
-        n += 1
-    return {"n": n, "matched": ok, "sample": f"first spectrum of every {every}th request"}
+        idx = np.array([o for o, _ in items])
+        got = np.array([p for _, p in items])
+        ref = np.array([x["params"] for x in oracle.fit_many(cfg, b.obs[idx], b.ivar[idx], basis,
+                                                             b.init[idx], threads=threads)])
+        ok += int(np.all(np.abs(got - ref)[:, :4] <= FIT_TOL, axis=1).sum())
+        if window:
+            ra = np.array([x["params"] for x in oracle.adam_fit_many(
+                cfg, b.obs[idx], b.ivar[idx], basis, b.init[idx], threads=threads, window=window,
+                tol=tol)])
+            ok_a += int(np.all(np.abs(got - ra)[:, :4] <= FIT_TOL, axis=1).sum())
+        n += len(items)
+    out = {"n": n, "matched": ok, "sample": f"first spectrum of every {every}th request"}
+    if window:
+        out["matched_oracle_adam_same_rules"] = ok_a
+    return out
 
 
 def main_serving(args):
@@ -616,12 +639,25 @@ def main():
         torch.cuda.empty_cache()
         print("[bench] autograd leg done", file=sys.stderr, flush=True)
 
-    # the served mixed-precision path: a Poisson stream through the fit server
+    # the served mixed-precision path: Poisson streams through the fit server,
+    # at the offered 20k spectra/s with the stopping rules of the optimisation
+    # stage (a request finishes when all its fits have stopped), and with 500
+    # fixed steps at a load the device sustains for this mix
     if extra:
         srv_leg, srv_meas, srv_where = serving_leg(banks, args.rate, args.serving_seconds,
-                                                   args.serving_warmup, "bf16x3")
-        srv_leg["alone_equals_mix"] = alone_equals_mix(banks, srv_meas, srv_where, "bf16x3")
-        print("[bench] serving leg done", file=sys.stderr, flush=True)
+                                                   args.serving_warmup, "bf16x3",
+                                                   stop_window=args.stop_window,
+                                                   stop_tol=args.stop_tol)
+        srv_leg["stopping_rules"] = {"window": args.stop_window, "tol": args.stop_tol}
+        srv_leg["alone_equals_mix"] = alone_equals_mix(banks, srv_meas, srv_where, "bf16x3",
+                                                       stop_window=args.stop_window,
+                                                       stop_tol=args.stop_tol)
+        fix_leg, fix_meas, fix_where = serving_leg(banks, args.serving_fixed_rate,
+                                                   args.serving_fixed_seconds,
+                                                   args.serving_warmup, "bf16x3", seed=1)
+        fix_leg["alone_equals_mix"] = alone_equals_mix(banks, fix_meas, fix_where, "bf16x3",
+                                                       n_per_shape=4)
+        print("[bench] serving legs done", file=sys.stderr, flush=True)
 
     # the plain method's small case: each spectrum fitted alone (B = 1)
     if extra:
@@ -745,6 +781,7 @@ def main():
             "latency_ms": {**pctl(lat_a), "unit": "ms per launch: J forward, dJ/du backward "
                                                   "through torch.autograd, then the covariance"}}
         out["serving_bf16x3"] = srv_leg
+        out["serving_bf16x3_fixed_steps"] = fix_leg
         out["single_fits_1550"] = {
             "value": args.single_fits / (lat_1.sum() / 1e3), "unit": "spectra/s",
             "spectra": args.single_fits, "n_pix": shape1.n_pix,
@@ -841,7 +878,10 @@ def main():
             out["single_fits_1550"]["oracle_match"] = {
                 "n": len(ref1), "matched": int(np.all(e1_ <= FIT_TOL, axis=1).sum()),
                 "max_abs_err": {k: float(v) for k, v in zip(PAR_NAMES[:4], e1_.max(axis=0))}}
-            out["serving_bf16x3"]["oracle_match"] = serving_oracle(banks, srv_meas, srv_where)
+            out["serving_bf16x3"]["oracle_match"] = serving_oracle(
+                banks, srv_meas, srv_where, window=args.stop_window, tol=args.stop_tol)
+            out["serving_bf16x3_fixed_steps"]["oracle_match"] = serving_oracle(
+                banks, fix_meas, fix_where)
             n3 = min(args.emulator_oracle_sample, B)
             cfg3 = oracle.Config.from_shape(shape, BOX_LO, BOX_HI, n_classes=3)
             t = time.perf_counter()
