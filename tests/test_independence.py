@@ -113,3 +113,25 @@ def test_built_libraries_do_not_link_each_other():
     lb, ob = open(lib, "rb").read(), open(olib, "rb").read()
     assert b"lasp_oracle" not in lb and b"orc_eval" not in lb
     assert b"lasp_fit_group" not in ob and b"liblasp.so" not in ob
+
+
+def test_bench_calls_the_oracle_only_after_its_timed_gpu_work():
+    """bench.py imports the oracle only inside functions, and main() names it
+    only after its last timed GPU call (the baseline and the checks run after
+    the measurements, never inside them)."""
+    path = os.path.join(ROOT, "bench.py")
+    tree = ast.parse(open(path).read(), path)
+    for node in tree.body:
+        if isinstance(node, (ast.Import, ast.ImportFrom)):
+            names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
+            assert not any(n.split(".")[0] == "oracle" for n in names), "module-level oracle import"
+    main = next(n for n in tree.body if isinstance(n, ast.FunctionDef) and n.name == "main")
+    gpu_calls = [n.lineno for n in ast.walk(main) if isinstance(n, ast.Call)
+                 and isinstance(n.func, (ast.Attribute, ast.Name))
+                 and getattr(n.func, "attr", getattr(n.func, "id", "")) in
+                 ("fit_group", "forward", "resample", "timed", "once", "serving_leg")]
+    oracle_refs = [n.lineno for n in ast.walk(main)
+                   if (isinstance(n, ast.Name) and n.id == "oracle")
+                   or (isinstance(n, ast.alias) and n.name == "oracle")]
+    assert gpu_calls and oracle_refs
+    assert min(oracle_refs) > max(gpu_calls), (min(oracle_refs), max(gpu_calls))
