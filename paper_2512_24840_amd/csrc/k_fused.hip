@@ -19,7 +19,9 @@
 //
 // One workgroup owns one spectrum; lane l owns pixels [17 l, 17 l + 17) (an
 // odd stride, so lanes hit distinct LDS banks).  Taps run in register blocks
-// of 8 against a 24-value window.
+// of 8 against a 24-value window.  The lag correlation takes g from
+// registers, so the g-bar row the transposed convolution reads replaces F'
+// in LDS once F' has been read for the last time.
 #include "lasp_internal.h"
 
 namespace lasp {
@@ -27,12 +29,21 @@ namespace {
 
 constexpr int kOffF = 16;  // F' column c lives at sF[kOffF + c]
 
+// Values per chunk of the moments' workgroup reduction: 8, or 4 for the
+// 512-thread pass (half the scratch).
+__host__ __device__ constexpr int moment_chunk(int nwaves) { return nwaves >= 8 ? 4 : 8; }
+
+// LDS of one workgroup.  Row region A holds, in turn, F' (column c at
+// kOffF + c) until the lag correlation has read it, then the g-bar row
+// (pixel j at 2M + j, j in [-2M, P + 2M + 32), zero outside [0, P)) for the
+// transposed convolution, then F-bar' on its way out.  Scratch region B
+// holds, in turn, the moments' reduction transposes, the lag correlation's
+// per-wave transposes [NW][kTB][64] and wave 0's mu / sigma sums.
 struct FusedLayout {
-  int rt_off;     // float offset of the per-wave transpose scratch [NW][kTB][64]
-  int sf_len;     // floats
-  int gb_off;     // float offset of the g-bar row (logical pixel j at gb_off + gb_base + j)
-  int gb_base;    // 2M
-  int gb_len;
+  int a_len;      // floats of region A
+  int gb_base;    // 2M: g-bar pixel j at sF[gb_base + j]
+  int b_off;      // float offset of region B
+  int b_len;      // floats of region B
   int ks;         // taps buffer stride per arm
   int k_off;      // float offset of the taps
   int r_off;      // float offset of per-wave R(m) partials [NW][n_arms][ks]
@@ -43,18 +54,21 @@ struct FusedLayout {
 
 __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwaves, int nmom_pad) {
   FusedLayout L;
-  const int cols = g.ldF > kNPL * g.block ? g.ldF : kNPL * g.block;
-  L.sf_len = kOffF + cols + 32;
+  const int f_len = kOffF + g.ldF + 32;
+  const int g_len = g.P + 4 * g.M + 32;
+  L.a_len = ((f_len > g_len ? f_len : g_len) + 3) & ~3;
   L.gb_base = 2 * g.M;
-  L.gb_len = g.P + 4 * g.M + 32;
-  if (L.gb_len < nwaves * 1024) L.gb_len = nwaves * 1024;  // also the moments' transpose scratch
-  L.gb_off = (L.sf_len + 3) & ~3;
+  const int mom = nwaves * moment_chunk(nwaves) * 64 * 2;  // doubles as floats
+  const int lag = nwaves * kTB * 64;
+  const int musig = 2 * (8 * 64 + 8);                     // wave_sum_lds scratch + sums
+  L.b_len = mom > lag ? mom : lag;
+  if (L.b_len < musig) L.b_len = musig;
+  L.b_off = L.a_len;
   L.ks = ((2 * g.M + 1 + 7) & ~7) + 8;
-  L.k_off = (L.gb_off + L.gb_len + 3) & ~3;
+  L.k_off = L.b_off + L.b_len;
   L.r_off = L.k_off + g.n_arms * L.ks;
   L.rs_off = L.r_off + nwaves * g.n_arms * L.ks;
-  L.rt_off = L.rs_off + g.n_arms * L.ks;
-  int fl_end = L.rt_off + nwaves * kTB * 64;
+  const int fl_end = L.rs_off + g.n_arms * L.ks;
   L.d_off = ((fl_end * 4) + 15) & ~15;
   // doubles: reduction scratch [nwaves][64], moments [nmom_pad], b [32],
   // scalars [32] (flag, float b copy, per-arm H and sigma)
@@ -67,21 +81,29 @@ __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwave
 // status with those of this pass.  0 (the passes of the Adam steps): the
 // status is left alone, so a condition seen only on the way does not reach
 // the result.
+//
+// Four waves per SIMD: the register budget is held to 128 per lane, so with
+// the LDS above four 256-thread or two 512-thread workgroups share a CU.  The
+// price is a few spills: at 3,900 pixels, 9 of a lane's 17 (o/w, W w^2)
+// pairs are parked in scratch between the moments and the residual (one
+// store and one load each per pass); measured faster than three waves per
+// SIMD without spills, for both pixel counts.
 template <int BLOCK, int ND, bool ADJ, bool MULTI>
-__global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *model_out,
-                                                 int set_status) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(
+    Geometry g, State s, float *model_out, int set_status) {
   constexpr int NW = BLOCK / 64;
   constexpr int NNU = 2 * ND - 1;  // nu_0 .. nu_{2D}
   constexpr int NMOM = NNU + ND;   // plus r_0 .. r_D
   constexpr int NWIN = kNPL + kTB - 1;
   extern __shared__ __align__(16) unsigned char smem[];
   const FusedLayout L = fused_layout(g, NW, NMOM);
-  float *sF = reinterpret_cast<float *>(smem);
-  float *sGb = sF + L.gb_off + L.gb_base;  // sGb[j], j in [-2M, P + 2M + 32)
+  float *sF = reinterpret_cast<float *>(smem);  // region A
+  float *sGb = sF + L.gb_base;  // sGb[j], j in [-2M, P + 2M + 32), once F' is read
+  float *sB = sF + L.b_off;     // region B
   float *sK = sF + L.k_off;
   float *sRp = sF + L.r_off;
   float *sRs = sF + L.rs_off;
-  float *sRt = sF + L.rt_off + (threadIdx.x >> 6) * (kTB * 64);
+  float *sRt = sB + (threadIdx.x >> 6) * (kTB * 64);
   double *sRed = reinterpret_cast<double *>(smem + L.d_off);
   double *sMom = sRed + NW * 64;
   double *sBd = sMom + NMOM;
@@ -124,7 +146,6 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     *reinterpret_cast<float4 *>(sF + kOffF + 4 * min(tid + k * BLOCK, n4 - 1)) = fst[k];
   for (int q = tid; q < kOffF; q += BLOCK) sF[q] = 0.f;
   for (int q = tid; q < 32; q += BLOCK) sF[kOffF + g.ldF + q] = 0.f;
-  for (int q = tid; q < L.gb_len; q += BLOCK) sF[L.gb_off + q] = 0.f;
   for (int q = tid; q < NW * g.n_arms * L.ks; q += BLOCK) sRp[q] = 0.f;
 
   // ---- Eq. 5 kernel parameters: mu, sigma in pixels, H per arm (FP64) ----
@@ -220,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
   //      in FP32; the sums over lanes and waves, the combination and the
   //      solve are FP64.
   {
-    double *scr = reinterpret_cast<double *>(sF + L.gb_off);
+    double *scr = reinterpret_cast<double *>(sB);
     const float two_over_p = 2.f / (float)P;
     const float x0 = fmaf((float)j0, two_over_p, -1.f);
 #pragma unroll
@@ -262,8 +283,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
     for (int k = 1; k < ND; ++k) acc[ND - 1 + k] = q[k];
 #pragma unroll
     for (int k = 0; k < ND; ++k) acc[NNU + k] = rr[k];
-    block_sum_lds<NW, NMOM>(acc, scr, sRed, sMom, lane, wave);
-    for (int q2 = tid; q2 < L.gb_len; q2 += BLOCK) sF[L.gb_off + q2] = 0.f;
+    block_sum_lds<NW, NMOM, moment_chunk(NW)>(acc, scr, sRed, sMom, lane, wave);
   }
 
   // ---- normal equations A b = r (A_mn = (nu_{m+n} + nu_|m-n|)/2), solved
@@ -343,7 +363,6 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       cmin = fminf(cmin, j < P ? C : INFINITY);
       if (j < P) {
         if (model_out) model_out[(size_t)spec * P + j] = mdl * wsc;
-        if (ADJ) sGb[j] = gb[i];
       }
     }
   }
@@ -427,7 +446,14 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       }
     }
   }
-  __syncthreads();
+  __syncthreads();  // every read of F' is done: region A takes the g-bar row
+  if (has_pix) {
+#pragma unroll
+    for (int i = 0; i < kNPL; ++i)
+      if (j0 + i < P) sGb[j0 + i] = gb[i];
+  }
+  for (int q = tid; q < 2 * M; q += BLOCK) sGb[q - 2 * M] = 0.f;
+  for (int q = tid; q < 2 * M + 32; q += BLOCK) sGb[P + q] = 0.f;
   for (int q = tid; q < g.n_arms * L.ks; q += BLOCK) {
     float acc = 0.f;
 #pragma unroll
@@ -453,10 +479,10 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
         rgd2 += R * G * d * d;
       }
       {
-        // F' in LDS is no longer read: its space is this wave's scratch
+        // region B is free once the lag correlation is done
         const double part[5] = {s1, s2, rg, rgd, rgd2};
-        double *tot = reinterpret_cast<double *>(sF) + 512;
-        wave_sum_lds<5>(part, reinterpret_cast<double *>(sF), tot, lane);
+        double *tot = reinterpret_cast<double *>(sB) + 512;
+        wave_sum_lds<5>(part, reinterpret_cast<double *>(sB), tot, lane);
         s1 = tot[0];
         s2 = tot[1];
         rg = tot[2];
@@ -518,9 +544,10 @@ __global__ __launch_bounds__(BLOCK) void k_fused(Geometry g, State s, float *mod
       }
     }
   }
-  __syncthreads();  // every read of F' in sF is done
+  __syncthreads();  // every read of the g-bar row is done: region A takes F-bar'
 #pragma unroll
-  for (int i = 0; i < kNPL; ++i) sF[kOffF + c0 + i] = (c0 + i < g.Pe) ? fb[i] : 0.f;
+  for (int i = 0; i < kNPL; ++i)
+    if (c0 + i < g.ldF) sF[kOffF + c0 + i] = (c0 + i < g.Pe) ? fb[i] : 0.f;
   __syncthreads();
   {
     float4 *dst = reinterpret_cast<float4 *>(s.fbar + (size_t)spec * g.ldF);

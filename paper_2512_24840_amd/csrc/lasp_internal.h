@@ -405,27 +405,37 @@ __device__ inline void wave_sum_lds(const double (&acc)[NV], double *scratch, do
   }
 }
 
-// Sum of NV per-lane doubles over the workgroup through LDS: eight values at
-// a time are transposed through scratch[wave][8][64] (one wave's region is
-// 4 KB), each group of eight lanes adds one value's 64 partials, then the
-// waves' results are added in a fixed order.  out[0..NV) is valid for every
-// thread after the call.  Deterministic.
-template <int NW, int NV, typename T>
+// Sum of NV per-lane values over the workgroup through LDS: CH values (8 or
+// 4) at a time are widened to FP64 and transposed through
+// scratch[wave][CH][64] (CH x 512 bytes per wave), each group of 64 / CH
+// lanes adds one value's 64 partials, then the waves' results are added in a
+// fixed order.  out[0..NV) is valid for every thread after the call.
+// Deterministic.
+template <int NW, int NV, int CH = 8, typename T>
 __device__ inline void block_sum_lds(const T (&acc)[NV], double *scratch, double *red,
                                      double *out, int lane, int wave) {
-  double *sc = scratch + wave * 512;
-  const int tt = lane >> 3, part = lane & 7;
+  static_assert(CH == 8 || CH == 4, "chunks of 8 or 4 values");
+  constexpr int G = 64 / CH;  // lanes per value
+  double *sc = scratch + wave * CH * 64;
+  const int tt = lane / G, part = lane % G;
 #pragma unroll
-  for (int c = 0; c < (NV + 7) / 8; ++c) {
-    // FP32 partials are widened 8 at a time, so few doubles are live at once
+  for (int c = 0; c < (NV + CH - 1) / CH; ++c) {
+    // FP32 partials are widened CH at a time, so few doubles are live at once
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-      sc[t * 64 + lane] = (8 * c + t < NV) ? (double)acc[(8 * c + t) % NV] : 0.0;
+    for (int t = 0; t < CH; ++t)
+      sc[t * 64 + lane] = (CH * c + t < NV) ? (double)acc[(CH * c + t) % NV] : 0.0;
     wave_lds_sync();
-    const double *row = sc + tt * 64 + 8 * part;
-    double v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));
-    v = group8_sum(v);
-    if (part == 0) red[wave * 64 + 8 * c + tt] = v;
+    const double *row = sc + tt * 64 + CH * part;
+    double v;
+    if constexpr (CH == 8) {
+      v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));
+      v = group8_sum(v);
+    } else {
+      v = (row[0] + row[1]) + (row[2] + row[3]);
+      v = group8_sum(v);
+      v += dpp_mov<0x140>(v);  // row_mirror: the two 8-lane halves of the row
+    }
+    if (part == 0) red[wave * 64 + CH * c + tt] = v;
     wave_lds_sync();
   }
   __syncthreads();
