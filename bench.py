@@ -20,9 +20,9 @@ with its own timing and oracle check:
                   every fitted parameter
   autograd_65536  65,536 x 3,900 px forward + adjoint through the
                   torch.autograd.Function, then the covariance
-  serving         Poisson streams of fit requests through the library's fit
-                  server: 20k spectra/s with the stopping rules (60 s measured
-                  after 5 s of warm-up), and 500 fixed steps at 10k spectra/s
+  serving         Poisson streams of 20k spectra/s through the library's fit
+                  server: 500 Adam steps per fit (60 s measured after 5 s of
+                  warm-up), and with the stopping rules (20 s)
 plus the stopping rules, Clean, Levenberg-Marquardt, three-class emulator,
 resampling and group-size legs.
 """
@@ -91,10 +91,8 @@ def parse(argv=None):
                    help="grouped run: measured seconds of the served stream leg")
     p.add_argument("--serving-warmup", type=float, default=5.0,
                    help="seconds of the served stream before the measured window")
-    p.add_argument("--serving-fixed-rate", type=float, default=10000.0,
-                   help="offered spectra/s of the fixed-step served stream leg")
-    p.add_argument("--serving-fixed-seconds", type=float, default=20.0,
-                   help="measured seconds of the fixed-step served stream leg")
+    p.add_argument("--serving-rules-seconds", type=float, default=20.0,
+                   help="measured seconds of the served stream leg with the stopping rules")
     p.add_argument("--emulator-oracle-sample", type=int, default=48,
                    help="emulator leg: spectra checked against the oracle's 3-class fit")
     p.add_argument("--large-spectra", type=int, default=262144,
@@ -639,24 +637,23 @@ def main():
         torch.cuda.empty_cache()
         print("[bench] autograd leg done", file=sys.stderr, flush=True)
 
-    # the served mixed-precision path: Poisson streams through the fit server,
-    # at the offered 20k spectra/s with the stopping rules of the optimisation
-    # stage (a request finishes when all its fits have stopped), and with 500
-    # fixed steps at a load the device sustains for this mix
+    # the served mixed-precision path: Poisson streams of 20k spectra/s
+    # through the fit server, with 500 Adam steps per fit, and with the
+    # stopping rules of the optimisation stage (a request finishes when all
+    # its fits have stopped)
     if extra:
         srv_leg, srv_meas, srv_where = serving_leg(banks, args.rate, args.serving_seconds,
+                                                   args.serving_warmup, "bf16x3")
+        srv_leg["alone_equals_mix"] = alone_equals_mix(banks, srv_meas, srv_where, "bf16x3")
+        rul_leg, rul_meas, rul_where = serving_leg(banks, args.rate, args.serving_rules_seconds,
                                                    args.serving_warmup, "bf16x3",
                                                    stop_window=args.stop_window,
-                                                   stop_tol=args.stop_tol)
-        srv_leg["stopping_rules"] = {"window": args.stop_window, "tol": args.stop_tol}
-        srv_leg["alone_equals_mix"] = alone_equals_mix(banks, srv_meas, srv_where, "bf16x3",
+                                                   stop_tol=args.stop_tol, seed=1)
+        rul_leg["stopping_rules"] = {"window": args.stop_window, "tol": args.stop_tol}
+        rul_leg["alone_equals_mix"] = alone_equals_mix(banks, rul_meas, rul_where, "bf16x3",
+                                                       n_per_shape=8,
                                                        stop_window=args.stop_window,
                                                        stop_tol=args.stop_tol)
-        fix_leg, fix_meas, fix_where = serving_leg(banks, args.serving_fixed_rate,
-                                                   args.serving_fixed_seconds,
-                                                   args.serving_warmup, "bf16x3", seed=1)
-        fix_leg["alone_equals_mix"] = alone_equals_mix(banks, fix_meas, fix_where, "bf16x3",
-                                                       n_per_shape=4)
         print("[bench] serving legs done", file=sys.stderr, flush=True)
 
     # the plain method's small case: each spectrum fitted alone (B = 1)
@@ -781,7 +778,7 @@ def main():
             "latency_ms": {**pctl(lat_a), "unit": "ms per launch: J forward, dJ/du backward "
                                                   "through torch.autograd, then the covariance"}}
         out["serving_bf16x3"] = srv_leg
-        out["serving_bf16x3_fixed_steps"] = fix_leg
+        out["serving_bf16x3_stopping_rules"] = rul_leg
         out["single_fits_1550"] = {
             "value": args.single_fits / (lat_1.sum() / 1e3), "unit": "spectra/s",
             "spectra": args.single_fits, "n_pix": shape1.n_pix,
@@ -878,10 +875,9 @@ def main():
             out["single_fits_1550"]["oracle_match"] = {
                 "n": len(ref1), "matched": int(np.all(e1_ <= FIT_TOL, axis=1).sum()),
                 "max_abs_err": {k: float(v) for k, v in zip(PAR_NAMES[:4], e1_.max(axis=0))}}
-            out["serving_bf16x3"]["oracle_match"] = serving_oracle(
-                banks, srv_meas, srv_where, window=args.stop_window, tol=args.stop_tol)
-            out["serving_bf16x3_fixed_steps"]["oracle_match"] = serving_oracle(
-                banks, fix_meas, fix_where)
+            out["serving_bf16x3"]["oracle_match"] = serving_oracle(banks, srv_meas, srv_where)
+            out["serving_bf16x3_stopping_rules"]["oracle_match"] = serving_oracle(
+                banks, rul_meas, rul_where, window=args.stop_window, tol=args.stop_tol)
             n3 = min(args.emulator_oracle_sample, B)
             cfg3 = oracle.Config.from_shape(shape, BOX_LO, BOX_HI, n_classes=3)
             t = time.perf_counter()
