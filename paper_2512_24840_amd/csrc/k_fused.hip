@@ -29,10 +29,6 @@ namespace {
 
 constexpr int kOffF = 16;  // F' column c lives at sF[kOffF + c]
 
-// Values per chunk of the moments' workgroup reduction: 8, or 4 for the
-// 512-thread pass (half the scratch).
-__host__ __device__ constexpr int moment_chunk(int nwaves) { return nwaves >= 8 ? 4 : 8; }
-
 // LDS of one workgroup.  Row region A holds, in turn, F' (column c at
 // kOffF + c) until the lag correlation has read it, then the g-bar row
 // (pixel j at 2M + j, j in [-2M, P + 2M + 32), zero outside [0, P)) for the
@@ -58,7 +54,7 @@ __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwave
   const int g_len = g.P + 4 * g.M + 32;
   L.a_len = ((f_len > g_len ? f_len : g_len) + 3) & ~3;
   L.gb_base = 2 * g.M;
-  const int mom = nwaves * moment_chunk(nwaves) * 64 * 2;  // doubles as floats
+  const int mom = nwaves * 8 * 64;                          // FP32 moment transposes
   const int lag = nwaves * kTB * 64;
   const int musig = 2 * (8 * 64 + 8);                     // wave_sum_lds scratch + sums
   L.b_len = mom > lag ? mom : lag;
@@ -84,10 +80,10 @@ __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwave
 //
 // Four waves per SIMD: the register budget is held to 128 per lane, so with
 // the LDS above four 256-thread or two 512-thread workgroups share a CU.  The
-// price is a few spills: at 3,900 pixels, 9 of a lane's 17 (o/w, W w^2)
-// pairs are parked in scratch between the moments and the residual (one
-// store and one load each per pass); measured faster than three waves per
-// SIMD without spills, for both pixel counts.
+// price is a few spills: at 3,900 pixels 40 bytes per lane (some of the
+// lane's (o/w, W w^2) pairs, parked in scratch between the moments and the
+// residual: one store and one load each per pass); measured faster than
+// three waves per SIMD without spills, for both pixel counts.
 template <int BLOCK, int ND, bool ADJ, bool MULTI>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_fused(
     Geometry g, State s, float *model_out, int set_status) {
@@ -238,10 +234,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   //      (n <= D), in one pass over the lane's pixels with T_0 .. T_D only:
   //      T_{D+k} = 2 T_D T_k - T_{D-k}, so nu_{D+k} = 2 q_k - nu_{D-k} with
   //      q_k = sum W F''^2 T_D T_k (k = 1..D).  Each lane sums its 17 pixels
-  //      in FP32; the sums over lanes and waves, the combination and the
-  //      solve are FP64.
+  //      in FP32, eight lanes' sums are added in FP32 on their way through
+  //      LDS; the sums over those groups and the waves, the combination and
+  //      the solve are FP64.
   {
-    double *scr = reinterpret_cast<double *>(sB);
     const float two_over_p = 2.f / (float)P;
     const float x0 = fmaf((float)j0, two_over_p, -1.f);
 #pragma unroll
@@ -283,7 +279,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     for (int k = 1; k < ND; ++k) acc[ND - 1 + k] = q[k];
 #pragma unroll
     for (int k = 0; k < ND; ++k) acc[NNU + k] = rr[k];
-    block_sum_lds<NW, NMOM, moment_chunk(NW)>(acc, scr, sRed, sMom, lane, wave);
+    block_sum_lds_f32<NW, NMOM>(acc, sB, sRed, sMom, lane, wave);
   }
 
   // ---- normal equations A b = r (A_mn = (nu_{m+n} + nu_|m-n|)/2), solved

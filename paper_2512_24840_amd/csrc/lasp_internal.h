@@ -405,37 +405,61 @@ __device__ inline void wave_sum_lds(const double (&acc)[NV], double *scratch, do
   }
 }
 
-// Sum of NV per-lane values over the workgroup through LDS: CH values (8 or
-// 4) at a time are widened to FP64 and transposed through
-// scratch[wave][CH][64] (CH x 512 bytes per wave), each group of 64 / CH
-// lanes adds one value's 64 partials, then the waves' results are added in a
-// fixed order.  out[0..NV) is valid for every thread after the call.
-// Deterministic.
-template <int NW, int NV, int CH = 8, typename T>
+// Sum of NV per-lane values over the workgroup through LDS: eight values at
+// a time are widened to FP64 and transposed through scratch[wave][8][64]
+// (one wave's region is 4 KB), each group of eight lanes adds one value's 64
+// partials, then the waves' results are added in a fixed order.  out[0..NV)
+// is valid for every thread after the call.  Deterministic.
+template <int NW, int NV, typename T>
 __device__ inline void block_sum_lds(const T (&acc)[NV], double *scratch, double *red,
                                      double *out, int lane, int wave) {
-  static_assert(CH == 8 || CH == 4, "chunks of 8 or 4 values");
-  constexpr int G = 64 / CH;  // lanes per value
-  double *sc = scratch + wave * CH * 64;
-  const int tt = lane / G, part = lane % G;
+  double *sc = scratch + wave * 512;
+  const int tt = lane >> 3, part = lane & 7;
 #pragma unroll
-  for (int c = 0; c < (NV + CH - 1) / CH; ++c) {
-    // FP32 partials are widened CH at a time, so few doubles are live at once
+  for (int c = 0; c < (NV + 7) / 8; ++c) {
+    // FP32 partials are widened 8 at a time, so few doubles are live at once
 #pragma unroll
-    for (int t = 0; t < CH; ++t)
-      sc[t * 64 + lane] = (CH * c + t < NV) ? (double)acc[(CH * c + t) % NV] : 0.0;
+    for (int t = 0; t < 8; ++t)
+      sc[t * 64 + lane] = (8 * c + t < NV) ? (double)acc[(8 * c + t) % NV] : 0.0;
     wave_lds_sync();
-    const double *row = sc + tt * 64 + CH * part;
-    double v;
-    if constexpr (CH == 8) {
-      v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));
-      v = group8_sum(v);
-    } else {
-      v = (row[0] + row[1]) + (row[2] + row[3]);
-      v = group8_sum(v);
-      v += dpp_mov<0x140>(v);  // row_mirror: the two 8-lane halves of the row
-    }
-    if (part == 0) red[wave * 64 + CH * c + tt] = v;
+    const double *row = sc + tt * 64 + 8 * part;
+    double v = ((row[0] + row[1]) + (row[2] + row[3])) + ((row[4] + row[5]) + (row[6] + row[7]));
+    v = group8_sum(v);
+    if (part == 0) red[wave * 64 + 8 * c + tt] = v;
+    wave_lds_sync();
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w * 64 + t];
+    out[t] = s;
+  }
+  __syncthreads();
+}
+
+// block_sum_lds for FP32 partials: eight values at a time go through
+// scratch[wave][8][64] as FP32 (2 KB per wave; half the registers and LDS of
+// widening first); each group of eight lanes adds one value's eight-lane
+// runs in FP32 and the rest -- across the groups, then the waves -- in FP64,
+// in a fixed order.  out[0..NV) is
+// valid for every thread after the call.  Deterministic.
+template <int NW, int NV>
+__device__ inline void block_sum_lds_f32(const float (&acc)[NV], float *scratch, double *red,
+                                         double *out, int lane, int wave) {
+  float *sc = scratch + wave * 8 * 64;
+  const int tt = lane >> 3, part = lane & 7;
+#pragma unroll
+  for (int c = 0; c < (NV + 7) / 8; ++c) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) sc[t * 64 + lane] = (8 * c + t < NV) ? acc[(8 * c + t) % NV] : 0.f;
+    wave_lds_sync();
+    const float4 x0 = *reinterpret_cast<const float4 *>(sc + tt * 64 + 8 * part);
+    const float4 x1 = *reinterpret_cast<const float4 *>(sc + tt * 64 + 8 * part + 4);
+    double v = (double)(((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w)));
+    v = group8_sum(v);
+    if (part == 0) red[wave * 64 + 8 * c + tt] = v;
     wave_lds_sync();
   }
   __syncthreads();
