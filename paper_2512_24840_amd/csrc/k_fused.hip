@@ -22,12 +22,29 @@
 // of 8 against a 24-value window.  The lag correlation takes g from
 // registers, so the g-bar row the transposed convolution reads replaces F'
 // in LDS once F' has been read for the last time.
+#include <type_traits>
+
 #include "lasp_internal.h"
 
 namespace lasp {
 namespace {
 
 constexpr int kOffF = 16;  // F' column c lives at sF[kOffF + c]
+constexpr int kMid = kNPL / 2;  // each lane expands the continuum about its pixel j0 + kMid
+
+// [x^n] T_k(x) for k, n <= 10, from T_k = 2x T_{k-1} - T_{k-2}.
+struct ChebPow {
+  int c[11][11];
+};
+constexpr ChebPow make_cheb_pow() {
+  ChebPow t{};
+  t.c[0][0] = 1;
+  t.c[1][1] = 1;
+  for (int k = 2; k < 11; ++k)
+    for (int n = 0; n <= k; ++n) t.c[k][n] = (n > 0 ? 2 * t.c[k - 1][n - 1] : 0) - t.c[k - 2][n];
+  return t;
+}
+constexpr ChebPow kChebPow = make_cheb_pow();
 
 // LDS of one workgroup.  Row region A holds, in turn, F' (column c at
 // kOffF + c) until the lag correlation has read it, then the g-bar row
@@ -66,8 +83,8 @@ __host__ __device__ inline FusedLayout fused_layout(const Geometry &g, int nwave
   L.rs_off = L.r_off + nwaves * g.n_arms * L.ks;
   const int fl_end = L.rs_off + g.n_arms * L.ks;
   L.d_off = ((fl_end * 4) + 15) & ~15;
-  // doubles: reduction scratch [nwaves][64], moments [nmom_pad], b [32],
-  // scalars [32] (flag, float b copy, per-arm H and sigma)
+  // doubles: reduction scratch [nwaves][64], moments [nmom_pad], the
+  // continuum's power series [32], scalars [32] (flag, per-arm H and sigma)
   L.bytes = L.d_off + 8 * (nwaves * 64 + nmom_pad + 32 + 32);
   return L;
 }
@@ -102,9 +119,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   float *sRt = sB + (threadIdx.x >> 6) * (kTB * 64);
   double *sRed = reinterpret_cast<double *>(smem + L.d_off);
   double *sMom = sRed + NW * 64;
-  double *sBd = sMom + NMOM;
+  double *sBd = sMom + NMOM;  // continuum power series m_n h^n
   double *sScal = sBd + 32;
-  float *sBf = reinterpret_cast<float *>(sScal + 8);  // [16]
   int *sHa = reinterpret_cast<int *>(sScal + 16);      // [kMaxArms]
   double *sSp = sScal + 24;                            // [kMaxArms]
 
@@ -316,50 +332,83 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         a[k] = 0.0;
       }
     }
-    if (row) {
-      const double bi = ok ? a[ND] : 0.0;
-      sBd[lane] = bi;
-      sBf[lane] = (float)bi;
+    // The continuum as a power series in the pixel offset v = j - P/2 from
+    // the row's centre: x_j = h v with h = 2 / P, so C = sum_n m_n h^n v^n
+    // with m_n = sum_k b_k [x^n] T_k.  The coefficients m_n h^n go to LDS;
+    // each lane re-centres the series on its own pixels below.
+    const double bi = (row && ok) ? a[ND] : 0.0;
+    double bk[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) bk[k] = read_lane(bi, k);
+    const double h = 2.0 / (double)P;
+    double hn = 1.0;
+#pragma unroll
+    for (int n = 0; n < ND; ++n) {
+      double m = 0.0;
+#pragma unroll
+      for (int k = n; k < ND; k += 2) m = fma(bk[k], (double)kChebPow.c[k][n], m);
+      if (lane == n) sBd[n] = m * hn;
+      hn *= h;
     }
     if (lane == 0) sScal[0] = ok ? 1.0 : 0.0;
   }
   __syncthreads();
 
   // ---- Eq. 7 residual, Eq. 9 chi2, adjoint seed g = dJ/dF'' ---------------
-  const bool ok = sScal[0] != 0.0;
+  const bool ok = __builtin_amdgcn_readfirstlane((int)(sScal[0] != 0.0)) != 0;
   const int n_eff = s.neff[spec];
-  const float inv_neff = n_eff > 0 ? 1.f / (float)n_eff : 0.f;
+  const float gscale = n_eff > 0 ? -2.f / (float)n_eff : 0.f;
   const float wsc = s.wscale[spec];
   float gb[kNPL];
   float chi2_part = 0.f;  // this lane's 17 terms; lanes and waves add in FP64
   float cmin = INFINITY;
   {
-    float c[ND];
+    // Taylor coefficients of t -> C(x_{j0 + kMid} + h t): the series in v
+    // shifted to v0 = j0 + kMid - P/2 by repeated synthetic division (FP64),
+    // then evaluated by Horner in FP32 at t = i - kMid, |h t| <= 16 / P.
+    float cf[ND];
+    {
+      double a[ND];
 #pragma unroll
-    for (int k = 0; k < ND; ++k) c[k] = sBf[k];
-    const float two_over_p = 2.f / (float)P;
+      for (int n = 0; n < ND; ++n) a[n] = sBd[n];
+      const double v0 = (double)(j0 + kMid) - 0.5 * (double)P;
 #pragma unroll
-    for (int i = 0; i < kNPL; ++i) {
-      const int j = j0 + i;
-      const float x = fmaf((float)j, two_over_p, -1.f);
-      const float x2 = x + x;
-      float b1 = 0.f, b2 = 0.f;
+      for (int k = 0; k < ND - 1; ++k)
 #pragma unroll
-      for (int k = ND - 1; k >= 1; --k) {
-        const float bk = fmaf(x2, b1, c[k] - b2);
-        b2 = b1;
-        b1 = bk;
+        for (int n = ND - 2; n >= k; --n) a[n] = fma(v0, a[n + 1], a[n]);
+#pragma unroll
+      for (int n = 0; n < ND; ++n) cf[n] = (float)a[n];
+    }
+    auto residual = [&](auto inside) {
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i) {
+        const int j = j0 + i;
+        const float t = (float)(i - kMid);
+        float C = cf[ND - 1];
+#pragma unroll
+        for (int k = ND - 2; k >= 0; --k) C = fmaf(C, t, cf[k]);
+        const float mdl = C * fpp[i];
+        const float e = ow[i].x - mdl;
+        const float we = ow[i].y * e;
+        chi2_part = fmaf(we, e, chi2_part);
+        gb[i] = (we * C) * gscale;
+        if constexpr (decltype(inside)::value)
+          cmin = fminf(cmin, C);
+        else
+          cmin = fminf(cmin, j < P ? C : INFINITY);
+        if (model_out != nullptr) {
+          if (j < P) model_out[(size_t)spec * P + j] = mdl * wsc;
+        }
       }
-      const float C = fmaf(x, b1, c[0] - b2);  // Clenshaw sum of c_k T_k(x)
-      const float mdl = C * fpp[i];
-      const float e = ow[i].x - mdl;
-      const float we = ow[i].y * e;
-      chi2_part = fmaf(we, e, chi2_part);
-      gb[i] = ok ? -2.f * we * C * inv_neff : 0.f;
-      cmin = fminf(cmin, j < P ? C : INFINITY);
-      if (j < P) {
-        if (model_out) model_out[(size_t)spec * P + j] = mdl * wsc;
-      }
+    };
+    // a wave whose every pixel lies in the row needs no range test for cmin
+    if (__builtin_amdgcn_readfirstlane(wave + 1) * 64 * kNPL <= P)
+      residual(std::true_type{});
+    else
+      residual(std::false_type{});
+    if (!ok) {
+#pragma unroll
+      for (int i = 0; i < kNPL; ++i) gb[i] = 0.f;
     }
   }
   {
