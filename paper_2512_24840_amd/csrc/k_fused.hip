@@ -130,6 +130,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int P = g.P, M = g.M;
   const int j0 = tid * kNPL;           // first pixel (and basis column) of this lane
+  // waves whose every lane has kNPL pixels in the row skip the per-pixel
+  // range tests: wave-uniform branches
+  const bool pix_inside = (__builtin_amdgcn_readfirstlane(wave) + 1) * 64 * kNPL <= g.P;
+  auto branch = [](bool c, auto &&f) {
+    if (c)
+      f(std::true_type{});
+    else
+      f(std::false_type{});
+  };
   const bool has_pix = j0 < P;
   const int jr = has_pix ? j0 : 0;     // window origin kept in range for idle lanes
 
@@ -161,10 +170,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   for (int q = tid; q < NW * g.n_arms * L.ks; q += BLOCK) sRp[q] = 0.f;
 
   // ---- Eq. 5 kernel parameters: mu, sigma in pixels, H per arm (FP64) ----
+  // Wave 0's serial sections (these taps, the continuum solve, dJ/dmu and
+  // dJ/dsigma) run at raised wave priority: the other waves of the
+  // workgroup wait on them, the waves of other workgroups do not.
   const double rv = g.rv_lo + (u4 + 1.0) * g.rv_half;
   const double sg = g.sg_lo + (u5 + 1.0) * g.sg_half;
   const double mu = rv * g.inv_scale;
   if (wave == 0) {
+    __builtin_amdgcn_s_setprio(3);
     for (int a = 0; a < g.n_arms; ++a) {
       const double seff = g.bare ? sg : sqrt(sg * sg + g.arm_sig2[a]);
       double spx = seff * g.inv_scale;
@@ -198,6 +211,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
 
   // ---- arms touched by this wave's output pixels (wave uniform) ---------
@@ -302,18 +316,31 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   //      in FP64 by Gauss-Jordan elimination, lane i holding row i.  sMom
   //      holds nu_0..nu_D, then q_1..q_D with nu_{D+k} = 2 q_k - nu_{D-k}.
   if (wave == 0) {
+    __builtin_amdgcn_s_setprio(3);
     constexpr int D = ND - 1;
-    auto nu_at = [&](int l) {
-      return l <= D ? sMom[l] : 2.0 * sMom[l] - sMom[2 * D - l];
-    };
-    double a[ND + 1];
-    const bool row = lane < ND;
-#pragma unroll
-    for (int n = 0; n < ND; ++n) {
-      const int d = lane > n ? lane - n : n - lane;
-      a[n] = row ? 0.5 * (nu_at(min(lane + n, NNU - 1)) + nu_at(min(d, NNU - 1))) : 0.0;
+    // nu_0 .. nu_2D mirrored about index D (sNu[D + l] = sNu[D - l] = nu_l),
+    // so row i reads nu_{i+n} and nu_{|i-n|} at fixed offsets from sNu + i
+    double *sNu = sRed;  // [3 D + 1], free until the residual's chi2 sums
+    {
+      const int l = min(lane, NNU - 1);
+      const double lo = sMom[l], hi = sMom[l <= D ? l : 2 * D - l];
+      const double nu = l <= D ? lo : fma(2.0, lo, -hi);
+      if (lane < NNU) sNu[D + lane] = nu;
+      if (lane >= 1 && lane <= D) sNu[D - lane] = nu;
     }
-    a[ND] = row ? sMom[NNU + min(lane, ND - 1)] : 0.0;
+    // lanes past row D repeat row D; only rows 0..D are read or stored
+    const bool row = lane < ND;
+    double a[ND + 1];
+    a[ND] = sMom[NNU + min(lane, ND - 1)];
+    wave_lds_sync();
+    {
+      const double *nr = sNu + min(lane, ND - 1);
+#pragma unroll
+      for (int n = 0; n < ND; ++n) a[n] = 0.5 * (nr[D + n] + nr[D - n]);
+    }
+    // Gauss-Jordan without scaling the pivot rows: row k stays as it is and
+    // every other row loses its column-k entry; b_i = a_i[ND] / a_i[i] at
+    // the end.  The pivots are those of the scaled form.
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
@@ -321,36 +348,44 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 #pragma unroll
       for (int n = k; n <= ND; ++n) piv[n] = read_lane(a[n], k);
       ok = ok && (piv[k] > 0.0) && isfinite(piv[k]);
-      const double rp = 1.0 / piv[k];
-      if (lane == k) {
+      // 1 / pivot: the hardware estimate and two Newton steps
+      double rp = __builtin_amdgcn_rcp(piv[k]);
+      rp = fma(rp, fma(-piv[k], rp, 1.0), rp);
+      rp = fma(rp, fma(-piv[k], rp, 1.0), rp);
+      const double f = lane == k ? 0.0 : a[k] * rp;
 #pragma unroll
-        for (int n = k; n <= ND; ++n) a[n] *= rp;
-      } else {
-        const double f = a[k] * rp;
+      for (int n = k + 1; n <= ND; ++n) a[n] = fma(-f, piv[n], a[n]);
+    }
+    {
+      double dg = a[0];
 #pragma unroll
-        for (int n = k + 1; n <= ND; ++n) a[n] = fma(-f, piv[n], a[n]);
-        a[k] = 0.0;
-      }
+      for (int n = 1; n < ND; ++n) dg = lane == n ? a[n] : dg;
+      a[ND] = a[ND] / dg;
     }
     // The continuum as a power series in the pixel offset v = j - P/2 from
     // the row's centre: x_j = h v with h = 2 / P, so C = sum_n m_n h^n v^n
-    // with m_n = sum_k b_k [x^n] T_k.  The coefficients m_n h^n go to LDS;
-    // each lane re-centres the series on its own pixels below.
-    const double bi = (row && ok) ? a[ND] : 0.0;
+    // with m_n = sum_k b_k [x^n] T_k.  b goes through LDS to every lane of
+    // the wave, the coefficients m_n h^n back to LDS; each lane re-centres
+    // the series on its own pixels below.
+    if (row) sBd[16 + lane] = ok ? a[ND] : 0.0;
+    wave_lds_sync();
     double bk[ND];
 #pragma unroll
-    for (int k = 0; k < ND; ++k) bk[k] = read_lane(bi, k);
-    const double h = 2.0 / (double)P;
-    double hn = 1.0;
+    for (int k = 0; k < ND; ++k) bk[k] = sBd[16 + k];
+    double mm[ND];
 #pragma unroll
     for (int n = 0; n < ND; ++n) {
       double m = 0.0;
 #pragma unroll
       for (int k = n; k < ND; k += 2) m = fma(bk[k], (double)kChebPow.c[k][n], m);
-      if (lane == n) sBd[n] = m * hn;
-      hn *= h;
+      mm[n] = m * g.hpow[n];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int n = 0; n < ND; ++n) sBd[n] = mm[n];
     }
     if (lane == 0) sScal[0] = ok ? 1.0 : 0.0;
+    __builtin_amdgcn_s_setprio(0);
   }
   __syncthreads();
 
@@ -401,11 +436,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         }
       }
     };
-    // a wave whose every pixel lies in the row needs no range test for cmin
-    if (__builtin_amdgcn_readfirstlane(wave + 1) * 64 * kNPL <= P)
-      residual(std::true_type{});
-    else
-      residual(std::false_type{});
+    branch(pix_inside, residual);
     if (!ok) {
 #pragma unroll
       for (int i = 0; i < kNPL; ++i) gb[i] = 0.f;
@@ -447,8 +478,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const int H = __builtin_amdgcn_readfirstlane(sHa[a]), T = 2 * H + 1;
       float gm[kNPL];
       if constexpr (!multi) {
+        branch(pix_inside, [&](auto inside) {
 #pragma unroll
-        for (int i = 0; i < kNPL; ++i) gm[i] = has_pix ? gb[i] : 0.f;
+          for (int i = 0; i < kNPL; ++i)
+            gm[i] = (decltype(inside)::value || has_pix) ? gb[i] : 0.f;
+        });
       } else {
         const int lo = g.arm_start[a], hi = g.arm_start[a + 1];
 #pragma unroll
@@ -492,11 +526,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
   }
   __syncthreads();  // every read of F' is done: region A takes the g-bar row
-  if (has_pix) {
+  branch(pix_inside, [&](auto inside) {
 #pragma unroll
     for (int i = 0; i < kNPL; ++i)
-      if (j0 + i < P) sGb[j0 + i] = gb[i];
-  }
+      if (decltype(inside)::value || j0 + i < P) sGb[j0 + i] = gb[i];
+  });
   for (int q = tid; q < 2 * M; q += BLOCK) sGb[q - 2 * M] = 0.f;
   for (int q = tid; q < 2 * M + 32; q += BLOCK) sGb[P + q] = 0.f;
   for (int q = tid; q < g.n_arms * L.ks; q += BLOCK) {
@@ -509,6 +543,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
   // ---- dJ/dmu, dJ/dsigma per arm and the chain to u4, u5 (wave 0) -------
   if (wave == 0) {
+    __builtin_amdgcn_s_setprio(3);
     double g4 = 0.0, g5 = 0.0;
     for (int a = 0; a < g.n_arms; ++a) {
       const int H = __builtin_amdgcn_readfirstlane(sHa[a]), T = 2 * H + 1;
@@ -547,6 +582,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       s.g45[(size_t)spec * 2 + 0] = ok ? (float)g4 : 0.f;
       s.g45[(size_t)spec * 2 + 1] = ok ? (float)g5 : 0.f;
     }
+    __builtin_amdgcn_s_setprio(0);
   }
 
   // ---- transposed convolution F-bar'_c = sum_m G(m) g_{c+m-M} ------------

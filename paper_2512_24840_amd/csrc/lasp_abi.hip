@@ -308,6 +308,8 @@ int make_geometry(const lasp_opts *o, const double *wave_grid, Geometry *g) {
     g->arm_start[o->n_arms] = P;
   }
   g->inv_scale = 1.0 / (lasp::kCkms * lasp::kLn10 * dl);
+  g->hpow[0] = 1.0;
+  for (int n = 1; n < 11; ++n) g->hpow[n] = g->hpow[n - 1] * (2.0 / (double)P);
   g->rv_lo = o->box_lo[3];
   g->rv_half = 0.5 * (o->box_hi[3] - o->box_lo[3]);
   g->sg_lo = o->box_lo[4];

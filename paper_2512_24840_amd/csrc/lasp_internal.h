@@ -64,6 +64,7 @@ struct Geometry {
   int nb;                       // basis rows: kNB * n_classes
   double lt_lo, lt_half;        // log10 Teff = lt_lo + (u1 + 1) lt_half
   double edges[4];              // Teff regime edges (K) of the class blend
+  double hpow[11];              // h^n, h = 2 / P: pixel step of the continuum's x
 };
 
 // Per-spectrum state and scratch owned by the library.
