@@ -436,7 +436,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         }
       }
     };
-    branch(pix_inside, residual);
+    // (the three-arm kernel keeps one copy of the loop: two copies there
+    // moved its spills and measured slower)
+    if constexpr (MULTI)
+      residual(std::false_type{});
+    else
+      branch(pix_inside, residual);
     if (!ok) {
 #pragma unroll
       for (int i = 0; i < kNPL; ++i) gb[i] = 0.f;
