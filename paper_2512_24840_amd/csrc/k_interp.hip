@@ -487,7 +487,7 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
   constexpr int NG = (NB + 15) / 16;
   constexpr int NWV = 8;
   constexpr int kSLd = 36;                        // staging row stride (floats)
-  constexpr int kStage = 32 * kSLd;               // one wave's [32 rows][32 columns]
+  constexpr int kStage = 36 * kSLd;               // one wave's [32 + 4 rows][32 columns]
   constexpr int kRed = 32 * 16 * NG;              // one wave's partial sums
   constexpr int kBuf = NWV * (kStage > kRed ? kStage : kRed);
   __shared__ __align__(16) float sbuf[kBuf];      // staging, then the partial sums
@@ -622,8 +622,89 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
       step(q0, q1, fa, bv);
     }
   };
+  floatx4 acc4 = {0.f, 0.f, 0.f, 0.f};
   if constexpr (NB == kNB) {
-    run(IntC<0>{}, IntC<NG>{});
+    // Basis rows 0-15 as one 16-row group of 16x16x4 products; rows 16-19
+    // as sixteen 4x4x1 blocks, no zero rows: block b = g + 8 h (lanes 4b ..
+    // 4b + 3) takes spectra 4g .. 4g + 3 and the h-th 16 columns of each
+    // 32-column stage, so lane l supplies F-bar' of spectrum l & 31 and
+    // basis row 16 + (l & 3), and accumulates spectra 4g + r x row 16 + (l & 3).
+    const int hh = lane >> 5, r4 = lane & 31, j4 = lane & 3;
+    const float *b4 = s.basis + (size_t)(16 + j4) * g.ldF;
+    const float *fb4row = s.fbar + (size_t)work_spec(s, s0 + r4 < count ? s0 + r4 : s0) * g.ldF;
+    float *stg = sbuf + wave * kStage;
+    const float *rp[4];
+    bool rv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int ri = 8 * j + (lane >> 3);
+      rv[j] = s0 + ri < count;
+      rp[j] = s.fbar + (size_t)work_spec(s, rv[j] ? s0 + ri : s0) * g.ldF + 4 * (lane & 7);
+    }
+    // lanes 0-31 stage basis rows 16-19 of the stage (row 32 + (lane >> 3))
+    const float *bs = s.basis + (size_t)(16 + ((lane >> 3) & 3)) * g.ldF + 4 * (lane & 7);
+    int c = cb;
+    if (c + 32 <= ce) {
+      float4 fv[4], fs, bv[kU];
+      auto fetch = [&](int cc) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          fv[j] = rv[j] ? *reinterpret_cast<const float4 *>(rp[j] + cc) : make_float4(0.f, 0.f, 0.f, 0.f);
+        fs = lane < 32 ? *reinterpret_cast<const float4 *>(bs + cc) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bv[u] = *reinterpret_cast<const float4 *>(b_ptr[0] + cc + 16 * u + 4 * kq);
+      };
+      fetch(c);
+      for (; c + 32 <= ce; c += 32) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          *reinterpret_cast<float4 *>(stg + (8 * j + (lane >> 3)) * kSLd + 4 * (lane & 7)) = fv[j];
+        if (lane < 32) *reinterpret_cast<float4 *>(stg + (32 + (lane >> 3)) * kSLd + 4 * (lane & 7)) = fs;
+        float4 bcur[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bcur[u] = bv[u];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (c + 64 <= ce) fetch(c + 32);  // next stage
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          float4 fa[2], b16[NG];
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+            fa[rt] = *reinterpret_cast<const float4 *>(stg + (16 * rt + i_row) * kSLd + 16 * u + 4 * kq);
+          b16[0] = bcur[u];
+          step(IntC<0>{}, IntC<1>{}, fa, b16);
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const float4 a4 = *reinterpret_cast<const float4 *>(stg + r4 * kSLd + 16 * hh + 4 * qq);
+          const float4 w4 = *reinterpret_cast<const float4 *>(stg + (32 + j4) * kSLd + 16 * hh + 4 * qq);
+          acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.x, w4.x, acc4, 0, 0, 0);
+          acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.y, w4.y, acc4, 0, 0, 0);
+          acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.z, w4.z, acc4, 0, 0, 0);
+          acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.w, w4.w, acc4, 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    for (; c < ce; c += 16) {  // a 16-column tail: lanes of half 1 add zeros
+      float4 fa[2], bv[NG];
+      load(IntC<0>{}, IntC<1>{}, c + 4 * kq, fa, bv);
+      step(IntC<0>{}, IntC<1>{}, fa, bv);
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        float4 a4 = *reinterpret_cast<const float4 *>(fb4row + c + 4 * qq);
+        const float4 w4 = *reinterpret_cast<const float4 *>(b4 + c + 4 * qq);
+        if (hh) a4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.x, w4.x, acc4, 0, 0, 0);
+        acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.y, w4.y, acc4, 0, 0, 0);
+        acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.z, w4.z, acc4, 0, 0, 0);
+        acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(a4.w, w4.w, acc4, 0, 0, 0);
+      }
+    }
   } else {
     // an emulator class with zero weight and weight derivative for all 32
     // spectra (other Teff regimes) only ever multiplies its rows of
@@ -653,18 +734,37 @@ __global__ __launch_bounds__(512) void k_interp_bwd(Geometry g, State s, AdamCfg
     }
   }
   __syncthreads();  // every wave is done with its stage: the buffer takes the partial sums
+  if constexpr (NB == kNB) {
+    // rows 0-15 from the 16-row group; rows 16-19 from the 4x4 blocks, the
+    // two column halves in columns 16-19 and 20-23
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r) red[wave][16 * rt + 4 * kq + r][i_row] = acc[rt][0][r];
+    const int g4 = (lane >> 2) & 7;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) red[wave][16 * rt + 4 * kq + r][16 * q + i_row] = acc[rt][q][r];
+    for (int r = 0; r < 4; ++r) red[wave][4 * g4 + r][16 + (lane & 3) + 4 * (lane >> 5)] = acc4[r];
+  } else {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < NG; ++q) red[wave][16 * rt + 4 * kq + r][16 * q + i_row] = acc[rt][q][r];
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * NB; e += 512) {
     const int i = e / NB, k = e - i * NB;
-    float v = red[0][i][k];
+    float v;
+    if (NB == kNB && k >= 16) {
+      v = red[0][i][k] + red[0][i][k + 4];
 #pragma unroll
-    for (int w = 1; w < NWV; ++w) v += red[w][i][k];
+      for (int w = 1; w < NWV; ++w) v += red[w][i][k] + red[w][i][k + 4];
+    } else {
+      v = red[0][i][k];
+#pragma unroll
+      for (int w = 1; w < NWV; ++w) v += red[w][i][k];
+    }
     pb[i][k] = v;
   }
   __syncthreads();
