@@ -123,14 +123,23 @@ def fused_flops_per_spectrum(params, shape):
     return P * (6.0 * T + 2.0 * (3 * D + 2) + 2.0 * (D + 1) + 10.0), T
 
 
+def fused_build_sha():
+    """SHA-256 of the fused kernel's source and its extra compile flags: the
+    counters in profiles/ hold for that build only."""
+    from paper_2512_24840_amd.build import EXTRA_FLAGS
+
+    h = hashlib.sha256(open(FUSED_SRC, "rb").read())
+    h.update(("\n" + " ".join(EXTRA_FLAGS.get(os.path.basename(FUSED_SRC), []))).encode())
+    return h.hexdigest()
+
+
 def traffic_for(n_launch_bytes_alg):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current source of the fused kernel."""
+    taken on the current build of the fused kernel."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     info = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(open(FUSED_SRC, "rb").read()).hexdigest()
-    if info.get("source_sha256") != sha:
+    if info.get("source_sha256") != fused_build_sha():
         return None
     return info.get("bytes_per_launch")
 
