@@ -25,12 +25,13 @@ HIP_FLAGS = [
 
 
 # Per-source additions.  The fused pass is scheduled with the scheduler's
-# own register-pressure trackers: at its 128-register bound this cut its
-# spills from 48 to 28 bytes per lane (3,900 px; 112 to 84 at 7,800 px)
-# and its time by 3-4 % and 10 %, with the same results bit for bit.  The
-# covariance kernel spills more with it, so it stays off elsewhere.
+# own register-pressure trackers and its max-ILP strategy: at its
+# 128-register bound this cut its spills from 48 to 20 bytes per lane
+# (3,900 px; 112 to 84 at 7,800 px) and its time by 5 % and 14 %, with the
+# same results bit for bit.  Elsewhere it did not pay (the covariance
+# kernel spills more, the forward contraction ran slower), so it stays off.
 EXTRA_FLAGS = {
-    "k_fused.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"],
+    "k_fused.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1", "-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }
 
 
