@@ -4,7 +4,9 @@
 //          W F'' o against Chebyshev polynomials (per-lane FP32 sums over 17
 //          pixels, FP64 across lanes), normal equations solved in FP64
 //          (Gauss-Jordan, one lane per row)
-//   Eq. 7  residual e = o - C F'';  Eq. 9 chi2 = sum W e^2 (per spectrum)
+//   Eq. 7  residual e = o - C F'' (C by Horner in a power series of the
+//          pixel offset, re-centred on each lane's pixels);  Eq. 9
+//          chi2 = sum W e^2 (per spectrum)
 //   adjoint of J = chi2 / n_eff with the continuum at its least-squares
 //          value (envelope theorem): g_j = -2 W e C / n_eff, the lag
 //          correlation R(m) = sum_j g_j F'_{j-m+M} giving dJ/dmu and
