@@ -9,6 +9,7 @@ import torch
 
 import oracle
 import paper_2512_24840_amd as lasp
+from loss_history import gpu_losses
 from synth import BOX_HI, BOX_LO, make_basis, make_spectra, shape_by_name, wave_grid
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
@@ -66,35 +67,18 @@ def test_stopping_step_and_fit_match_oracle_adam(name):
 def test_stopping_step_is_the_rule_on_the_gpu_own_losses(name, w, tol, rule_seen):
     """The stopping step is an integer decided on floating-point losses, so
     the decision is checked in the kernel's own arithmetic: the losses
-    ell_t = sqrt(chi2 / n_eff) of the fixed-step fit after t = 0 .. T steps
-    (slot block t of a pool holds the batch with a limit of t steps and is
-    evaluated at its returned point), scanned by the oracle's rules, give
-    exactly the step and the rule at which the GPU stopped each fit; each
-    case sees its rule (flat loss, rising loss, step limit) at least once."""
+    ell_t = sqrt(chi2 / n_eff) of the fixed-step fit after t = 0 .. T steps,
+    scanned by the oracle's rules, give exactly the step and the rule at
+    which the GPU stopped each fit; each case sees its rule (flat loss,
+    rising loss, step limit) at least once."""
     print(f"[early stop: rules on the GPU's own losses] {name} B=12 W={w} tol={tol}", flush=True)
     shape, basis, batch = problem(name, 12, 41)
     p, st, steps = gpu_fit(shape, basis, batch, stop_window=w, stop_tol=tol)
     n, T = 12, int(steps.max())
-    obs, ivar, init, bas = (to_dev(batch.obs), to_dev(batch.ivar), to_dev(batch.init),
-                            to_dev(basis))
-    pool = lasp.Pool(wave_grid(shape), bas, n * (T + 1), margin=shape.margin,
-                     degree=shape.degree)
-    with torch.cuda.stream(pool.stream):
-        for t in range(T + 1):
-            pool.load(n * t, obs, ivar, init, t)
-        pool.step(n * (T + 1), T)
-        out = torch.empty((n * (T + 1), 5), dtype=torch.float32, device=DEV)
-        chi2 = torch.empty(n * (T + 1), dtype=torch.float64, device=DEV)
-        pool.finish(0, out, chi2=chi2)
-    pool.stream.synchronize()
-    pool.close()
     cfg = oracle.Config.from_shape(shape, BOX_LO, BOX_HI)
-    u0 = to_dev(cfg.normalise(batch.init).astype(np.float32))
-    n_eff = lasp.forward(obs, ivar, wave_grid(shape), bas, u0, margin=shape.margin,
-                         degree=shape.degree)["n_eff"].cpu().numpy()
-    torch.cuda.synchronize()
-    ell = np.sqrt(chi2.cpu().numpy().reshape(T + 1, n) / n_eff)
-    got = out.cpu().numpy().reshape(T + 1, n, 5)
+    ell, got, n_eff = gpu_losses(shape, to_dev(basis), to_dev(batch.obs), to_dev(batch.ivar),
+                                 to_dev(batch.init),
+                                 to_dev(cfg.normalise(batch.init).astype(np.float32)), T)
     # the rules are tested after t = 0 .. NMAX - 1 steps (none after the last)
     n_scan = min(T + 1, NMAX)
     rules = set()

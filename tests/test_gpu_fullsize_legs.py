@@ -11,6 +11,7 @@ import torch
 
 import oracle
 import paper_2512_24840_amd as lasp
+from loss_history import gpu_losses
 from synth import BOX_HI, BOX_LO, make_basis, make_spectra_parallel, shape_by_name, wave_grid
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
@@ -65,6 +66,22 @@ def test_stopping_rules_16384x3900_match_oracle_adam_on_sample(full):
         assert abs(int(steps[i]) - r["steps"]) <= max(10, 0.1 * r["steps"]), (i, steps[i], r["steps"])
         assert np.all(np.abs(p[i] - r["params"])[:4] <= FIT_TOL), (i, p[i], r["params"])
     say(f"  steps mean {steps.mean():.1f}, sampled stops within the bar of the oracle's")
+    # the step each sampled fit stopped at, decided in the kernels' own
+    # arithmetic: the oracle's rule scan over the GPU's losses of the same
+    # spectra after 0 .. T fixed steps gives it exactly
+    T = int(steps[idx].max())
+    _, _, _, _, d = full
+    ix = torch.from_numpy(idx).to(DEV)
+    ell, got, _ = gpu_losses(shape, d["basis"], d["obs"][ix].contiguous(),
+                             d["ivar"][ix].contiguous(), d["init"][ix].contiguous(),
+                             torch.from_numpy(cfg.normalise(batch.init[idx]).astype(np.float32)).to(DEV),
+                             T)
+    n_scan = min(T + 1, 500)
+    for k, i in enumerate(idx):
+        t_ref, rule = oracle.stop_step(np.ascontiguousarray(ell[:n_scan, k]), n_scan, 50, 1e-5)
+        assert t_ref == steps[i] and st[i] & RULE_BIT[rule], (i, steps[i], st[i], t_ref, rule)
+        assert np.array_equal(got[steps[i], k].astype(np.float64), p[i]), i
+    say("  the 32 sampled stops are the rules on the GPU's own losses exactly")
 
 
 def test_adam_and_lm_polish_16384x3900_reach_oracle_lm_on_sample(full):
