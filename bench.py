@@ -14,7 +14,9 @@ oracle's own rate on a bounded sample of the same spectra, with the fraction
 of that sample whose GPU parameters match the oracle's within the tolerances
 (Teff 2 K, log g and [Fe/H] 0.005 dex, RV 0.2 km/s).  Further legs, each
 with its own timing and oracle check:
-  single_fits     64 spectra of 1,550 px, each fitted alone (B = 1 calls)
+  single_fits     64 spectra of 1,550 px, each fitted alone (B = 1 calls):
+                  500 Adam steps, and the plain method's Levenberg-Marquardt
+                  fit (at most 200 iterations)
   bf16x3_262144   262,144 x 3,900 px with BF16x3 contractions, with the
                   error table against the oracle for model flux, chi2 and
                   every fitted parameter
@@ -685,6 +687,22 @@ def main():
             params_1.append(r1.params[0].cpu().numpy().astype(np.float64))
         params_1 = np.array(params_1)
         lat_1 = np.array(lat_1)
+        # the plain method: Levenberg-Marquardt from the start point, at most
+        # 200 iterations (the call stops enqueuing once the fit has stopped)
+        kw1lm = dict(kw1, polish_iters=200)
+        lasp.fit_group(*ones[0][:2], grid1, bas1, ones[0][2], 0, **kw1lm)
+        torch.cuda.synchronize()
+        lat_1lm, params_1lm, lim_1lm = [], [], 0
+        for o1, i1, n1 in ones:
+            e0.record(stream)
+            r1 = lasp.fit_group(o1, i1, grid1, bas1, n1, 0, **kw1lm)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            lat_1lm.append(e0.elapsed_time(e1))
+            params_1lm.append(r1.params[0].cpu().numpy().astype(np.float64))
+            lim_1lm += int((r1.status[0].item() & lasp.ST_POLISH_LIMIT) != 0)
+        params_1lm = np.array(params_1lm)
+        lat_1lm = np.array(lat_1lm)
 
     params = res.params.cpu().numpy().astype(np.float64)
     status = res.status.cpu().numpy()
@@ -793,6 +811,12 @@ def main():
             "spectra": args.single_fits, "n_pix": shape1.n_pix,
             "latency_ms": {**pctl(lat_1), "unit": "ms per fit (one spectrum per call, 500 "
                                                   "steps + covariance)"}}
+        out["single_fits_1550_lm"] = {
+            "value": args.single_fits / (lat_1lm.sum() / 1e3), "unit": "spectra/s",
+            "spectra": args.single_fits, "n_pix": shape1.n_pix, "max_lm_iters": 200,
+            "hit_iteration_limit": lim_1lm,
+            "latency_ms": {**pctl(lat_1lm), "unit": "ms per fit (one spectrum per call, "
+                                                    "Levenberg-Marquardt + covariance)"}}
         out["emulator_3class"] = {
             "value": B / t_3, "unit": "spectra/s", "ms_per_group_fit": t_3 * 1e3,
             "classes": 3, "basis_rows": 60, "adam_steps": args.adam_steps,
@@ -884,6 +908,10 @@ def main():
             out["single_fits_1550"]["oracle_match"] = {
                 "n": len(ref1), "matched": int(np.all(e1_ <= FIT_TOL, axis=1).sum()),
                 "max_abs_err": {k: float(v) for k, v in zip(PAR_NAMES[:4], e1_.max(axis=0))}}
+            e1lm = np.abs(params_1lm - np.array([r["params"] for r in ref1]))[:, :4]
+            out["single_fits_1550_lm"]["oracle_match"] = {
+                "n": len(ref1), "matched": int(np.all(e1lm <= FIT_TOL, axis=1).sum()),
+                "max_abs_err": {k: float(v) for k, v in zip(PAR_NAMES[:4], e1lm.max(axis=0))}}
             out["serving_bf16x3"]["oracle_match"] = serving_oracle(banks, srv_meas, srv_where)
             out["serving_bf16x3_stopping_rules"]["oracle_match"] = serving_oracle(
                 banks, rul_meas, rul_where, window=args.stop_window, tol=args.stop_tol)

@@ -128,7 +128,12 @@ extern "C" {
  *                  less than 1e-7, or when lambda exceeds 1e10
  *                  (LASP_ST_POLISH_LIMIT if the iteration limit came first).  The paper proposes adding curvature
  *                  information to its Adam stage (Section 4.5); n_steps = 0
- *                  with polish_iters > 0 is a plain LM fit.
+ *                  with polish_iters > 0 is a plain LM fit.  Every 4
+ *                  iterations the number of spectra still iterating is
+ *                  counted on the device; once a count reads 0 the call
+ *                  stops enqueuing iterations (it waits on its stream for
+ *                  the count of 4 iterations earlier), which changes no
+ *                  result: a stopped spectrum's iterations do nothing.
  *  clean_every, clean_max  the Clean strategy of Section 2.2 (steps 6 and 8):
  *                  after every clean_every Adam steps (at most clean_max
  *                  times; the paper's 30 and 11) the model at the current
@@ -148,6 +153,17 @@ extern "C" {
  *                  e1 <= T <= e2 and T >= e3, a linear blend in Teff across
  *                  (e0, e1) and (e2, e3).  BF16X3 supports one class only.
  *  class_edges     e0 < e1 < e2 < e3 in K (default 4000, 4550, 7000, 9000).
+ *  step_graph      1 (default): lasp_fit_group enqueues its Adam steps as
+ *                  replays of one HIP graph of 25 steps when no stopping
+ *                  rules, no Clean and one emulator class are asked for
+ *                  (the steps then launch the same kernels with the same
+ *                  arguments) and n_spec <= 4096 (larger groups launch
+ *                  long kernels); the graph is captured on first use and kept
+ *                  with the call's cached device scratch until the
+ *                  geometry, the buffers or the Adam settings change, and
+ *                  the results are those of launching each step's kernels
+ *                  (0).  Kernel timing (lasp_profile_enable) launches
+ *                  them one by one.
  */
 typedef struct lasp_opts {
   int32_t n_spec;
@@ -175,6 +191,7 @@ typedef struct lasp_opts {
   uint8_t *out_mask;
   int32_t n_classes;
   double class_edges[4];
+  int32_t step_graph;
 } lasp_opts;
 
 /* Defaults: n_basis 20, margin 64, degree 10, FP32, box

@@ -143,7 +143,30 @@ __global__ void k_lm_accept(Geometry g, State s, LmState lm, int last) {
   lm.flags[spec] = fl;
 }
 
+// Number of spectra whose polish has not stopped, into *lm.active (one
+// workgroup; the host reads it to stop enqueuing iterations).
+__global__ __launch_bounds__(1024) void k_lm_active(Geometry g, LmState lm) {
+  __shared__ int part[16];
+  int n = 0;
+  for (int i = threadIdx.x; i < g.B; i += 1024) n += (lm.flags[i] & kLmDone) ? 0 : 1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_down(n, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += part[w];
+    *lm.active = t;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_lm_active(const Geometry &g, const LmState &lm, hipStream_t st) {
+  hipLaunchKernelGGL(k_lm_active, dim3(1), dim3(1024), 0, st, g, lm);
+  return hipGetLastError();
+}
 
 hipError_t launch_lm_init(const Geometry &g, const LmState &lm, hipStream_t st) {
   hipLaunchKernelGGL(k_lm_init, dim3((g.B + kLmBlock - 1) / kLmBlock), dim3(kLmBlock), 0, st, g,

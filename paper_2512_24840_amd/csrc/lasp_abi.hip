@@ -45,6 +45,11 @@ struct Workspace {
   float *model = nullptr;  // [B][P] model for the Clean updates
   State s{};
   lasp::LmState lm{};
+  // a chunk of plain Adam steps as one HIP graph (lasp_fit_group), with the
+  // bytes of the arguments it was captured with
+  hipStream_t cap_st = nullptr;  // capture only: nothing runs on it
+  hipGraphExec_t steps_exec = nullptr;
+  std::vector<unsigned char> steps_key;
 };
 
 std::mutex g_mu;
@@ -88,6 +93,11 @@ void free_ws(Workspace *w) {
     if (e) (void)hipEventDestroy(e);
     e = nullptr;
   }
+  if (w->steps_exec) (void)hipGraphExecDestroy(w->steps_exec);
+  w->steps_exec = nullptr;
+  w->steps_key.clear();
+  if (w->cap_st) (void)hipStreamDestroy(w->cap_st);
+  w->cap_st = nullptr;
   w->s = State{};
   w->lm = lasp::LmState{};
   w->cap_B = w->cap_ow = w->cap_fp = w->cap_fbar = w->cap_basis = w->cap_hist = w->cap_lm = 0;
@@ -148,8 +158,11 @@ int ensure_buffers(Workspace *w, const Geometry &g, int fp_rows, int hist_w, hip
     if (r == hipSuccess) r = grow(l.u_trial, a5, need_lm * lasp::kNP);
     if (r == hipSuccess) r = grow(l.st_trial, a6, need_lm);
     if (r == hipSuccess) r = grow(l.need_jac, a7, need_lm);
-    if (r == hipSuccess) r = grow(l.flags, a8, need_lm);
-    if (r == hipSuccess) w->cap_lm = need_lm;
+    if (r == hipSuccess) r = grow(l.flags, a8, need_lm + 1);
+    if (r == hipSuccess) {
+      l.active = l.flags + need_lm;
+      w->cap_lm = need_lm;
+    }
   }
   if (r == hipSuccess) r = grow(s.ow, w->cap_ow, need_ow);
   if (r == hipSuccess) r = grow(s.fp, w->cap_fp, need_fp);
@@ -405,6 +418,8 @@ void prof_drain() {
 
 // Steps between two compactions of the active list (stopping rules on).
 constexpr int kCompactEvery = 16;
+// Polish iterations between two counts of the spectra still iterating.
+constexpr int kLmCheckEvery = 4;
 
 #define LASP_CHECK(call, what)                 \
   do {                                         \
@@ -519,6 +534,66 @@ size_t carve_forward_state(const Geometry &g, int fp_rows, int bf16, unsigned ch
   return off;
 }
 
+// Adam steps per replay of the cached step graph, and the largest group that
+// uses it: beyond that each step's kernels run long enough that launching
+// them one by one costs nothing (the replay measured 0.4 % slower at 16,384
+// spectra, 6 % faster for one spectrum).
+constexpr int kGraphSteps = 25;
+constexpr int kGraphMaxSpectra = 4096;
+
+// Enqueues chunks x kGraphSteps plain Adam steps (interpolator contraction,
+// fused pass, adjoint contraction + Adam; no stopping rules, one emulator
+// class, no Clean) on st as replays of one HIP graph.  The graph is captured
+// on the workspace's own stream (nothing runs there) and kept until the
+// arguments change: the kernels take (g, s, adam, bf16) by value, so equal
+// bytes of those mean an equal launch sequence.  The graph holds kernel
+// nodes only.
+int replay_steps(Workspace *w, const Geometry &g, const State &s, const lasp::AdamCfg &adam,
+                 int bf16, int chunks, hipStream_t st) {
+  std::vector<unsigned char> key(sizeof(Geometry) + sizeof(State) + sizeof(adam) + sizeof(int));
+  unsigned char *k = key.data();
+  memcpy(k, &g, sizeof(Geometry));
+  memcpy(k + sizeof(Geometry), &s, sizeof(State));
+  memcpy(k + sizeof(Geometry) + sizeof(State), &adam, sizeof(adam));
+  memcpy(k + sizeof(Geometry) + sizeof(State) + sizeof(adam), &bf16, sizeof(int));
+  if (!w->steps_exec || w->steps_key != key) {
+    if (w->steps_exec) (void)hipGraphExecDestroy(w->steps_exec);
+    w->steps_exec = nullptr;
+    w->steps_key.clear();
+    hipError_t e = hipSuccess;
+    if (!w->cap_st) e = hipStreamCreateWithFlags(&w->cap_st, hipStreamNonBlocking);
+    if (e != hipSuccess) return dev_fail(e, "step graph stream");
+    e = hipStreamBeginCapture(w->cap_st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return dev_fail(e, "step graph capture");
+    hipError_t le = hipSuccess;
+    for (int it = 0; it < kGraphSteps && le == hipSuccess; ++it) {
+      le = lasp::launch_interp_fwd(g, s, 0, bf16, w->cap_st);
+      if (le == hipSuccess) le = lasp::launch_fused(g, s, 1, nullptr, 0, w->cap_st);
+      if (le == hipSuccess) le = lasp::launch_interp_bwd(g, s, &adam, nullptr, bf16, w->cap_st);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(w->cap_st, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return dev_fail(le != hipSuccess ? le : e, "step graph capture");
+    }
+    e = hipGraphInstantiate(&w->steps_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      w->steps_exec = nullptr;
+      (void)hipGetLastError();
+      return dev_fail(e, "step graph instantiation");
+    }
+    w->steps_key = key;
+  }
+  for (int c = 0; c < chunks; ++c) {
+    hipError_t e = hipGraphLaunch(w->steps_exec, st);
+    if (e != hipSuccess) return dev_fail(e, "step graph launch");
+  }
+  return LASP_OK;
+}
+
 __global__ void k_zero16(uint4 *p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -557,6 +632,7 @@ void lasp_default_opts(lasp_opts *o) {
   o->n_classes = 1;
   const double edges[4] = {4000.0, 4550.0, 7000.0, 9000.0};
   for (int i = 0; i < 4; ++i) o->class_edges[i] = edges[i];
+  o->step_graph = 1;
 }
 
 const char *lasp_last_error(void) { return g_err.c_str(); }
@@ -652,13 +728,23 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
   }
   const lasp::AdamCfg adam{opts->lr, opts->beta1, opts->beta2, opts->eps, W, opts->stop_tol};
   s.fp_stride = g.ldF;
-  if (W > 0 && !w->h_active) {
+  if ((W > 0 || polish > 0) && !w->h_active) {
     hipError_t e = hipHostMalloc((void **)&w->h_active, 2 * sizeof(int));
     for (int k = 0; e == hipSuccess && k < 2; ++k)
       e = hipEventCreateWithFlags(&w->ev[k], hipEventDisableTiming);
     if (e != hipSuccess) return dev_fail(e, "active-list events");
   }
-  for (int it = 0; it < n_steps; ++it) {
+  int it0 = 0;
+  if (opts->step_graph && W == 0 && !regimes && ce == 0 && g_prof_mask.load() == 0 &&
+      n_steps >= kGraphSteps && g.B <= kGraphMaxSpectra) {
+    // the plain path launches the same three kernels with the same
+    // arguments at every step: whole chunks replay one cached graph (not
+    // while kernels are being timed, which brackets each launch)
+    it0 = n_steps / kGraphSteps * kGraphSteps;
+    rc = replay_steps(w, g, s, adam, bf16, n_steps / kGraphSteps, st);
+    if (rc) return rc;
+  }
+  for (int it = it0; it < n_steps; ++it) {
     if ((W > 0 || regimes) && (it > 0 || regimes) && it % kCompactEvery == 0) {
       // the spectra still stepping, listed so that the per-step kernels cover
       // those only (a fit's arithmetic does not depend on its place)
@@ -732,6 +818,22 @@ int lasp_fit_group(const float *obs, const float *ivar, const double *wave_grid,
       LASP_CHECK(lasp::launch_interp_fwd(g, trial, 0, bf16, st), "interpolator contraction");
       LASP_CHECK(lasp::launch_fused(g, trial, 0, nullptr, 1, st), "fused pass");
       LASP_CHECK(lasp::launch_lm_accept(g, s, lm, it == polish - 1, st), "polish accept");
+      if ((it + 1) % kLmCheckEvery == 0 && it + 1 < polish) {
+        // once every spectrum has stopped the remaining iterations change
+        // nothing: the host reads the count of kLmCheckEvery iterations
+        // earlier (the device is still working through the ones since) and
+        // stops enqueuing
+        const int slot = ((it + 1) / kLmCheckEvery) & 1;
+        LASP_CHECK(lasp::launch_lm_active(g, lm, st), "polish count");
+        LASP_CHECK(hipMemcpyAsync(w->h_active + slot, lm.active, sizeof(int),
+                                  hipMemcpyDeviceToHost, st),
+                   "polish count");
+        LASP_CHECK(hipEventRecord(w->ev[slot], st), "polish count event");
+        if (it + 1 >= 2 * kLmCheckEvery) {
+          LASP_CHECK(hipEventSynchronize(w->ev[slot ^ 1]), "polish count wait");
+          if (w->h_active[slot ^ 1] == 0) break;
+        }
+      }
     }
   }
   s.fp_stride = out_cov ? 4 * g.ldF : g.ldF;

@@ -107,6 +107,7 @@ struct LmState {
   uint32_t *st_trial;  // [B] status of the trial evaluation (discarded)
   int *need_jac;       // [B] 1: normal equations needed at the current u
   int *flags;          // [B] kLmDone
+  int *active;         // [1] spectra still iterating (k_lm_active)
 };
 
 // Inputs and outputs of the Clean mask kernel.  obs, ivar and model are
@@ -176,6 +177,7 @@ hipError_t launch_outputs(const Geometry &g, const State &s, double *chi2_out, f
                           int32_t *neff_out, uint32_t *status_out, hipStream_t st);
 hipError_t launch_lm_init(const Geometry &g, const LmState &lm, hipStream_t st);
 hipError_t launch_lm_solve(const Geometry &g, const State &s, const LmState &lm, hipStream_t st);
+hipError_t launch_lm_active(const Geometry &g, const LmState &lm, hipStream_t st);
 hipError_t launch_lm_accept(const Geometry &g, const State &s, const LmState &lm, int last,
                             hipStream_t st);
 hipError_t launch_clean(const Geometry &g, const CleanArgs &a, hipStream_t st);

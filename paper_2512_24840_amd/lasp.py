@@ -103,6 +103,7 @@ class LaspOpts(ctypes.Structure):
         ("out_mask", ctypes.c_void_p),
         ("n_classes", ctypes.c_int32),
         ("class_edges", ctypes.c_double * 4),
+        ("step_graph", ctypes.c_int32),
     ]
 
 
@@ -220,7 +221,8 @@ class Arms:
 def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
               betas=(0.9, 0.999), eps=1e-8, weight_quantile=0.5, arms: Arms | None = None,
               box=None, stream=None, stop_window=0, stop_tol=1e-5, polish_iters=0,
-              clean_every=0, clean_max=11, n_classes=1, class_edges=None) -> LaspOpts:
+              clean_every=0, clean_max=11, n_classes=1, class_edges=None,
+              step_graph=True) -> LaspOpts:
     o = LaspOpts()
     load().lasp_default_opts(ctypes.byref(o))
     o.n_spec, o.n_pix, o.margin, o.degree = int(n_spec), int(n_pix), int(margin), int(degree)
@@ -232,6 +234,7 @@ def make_opts(n_spec, n_pix, *, margin=64, degree=10, precision="fp32", lr=1e-2,
     o.clean_every, o.clean_max = int(clean_every), int(clean_max)
     o.n_classes = int(n_classes)
     o.n_basis = N_BASIS * int(n_classes)
+    o.step_graph = int(bool(step_graph))
     if class_edges is not None:
         for i in range(4):
             o.class_edges[i] = float(class_edges[i])
@@ -270,14 +273,16 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
               margin=64, degree=10, precision="fp32", lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
               weight_quantile=0.5, arms: Arms | None = None, box=None, stream=None,
               stop_window=0, stop_tol=1e-5, polish_iters=0, clean_every=0, clean_max=11,
-              want_mask=False, n_classes=1, class_edges=None,
+              want_mask=False, n_classes=1, class_edges=None, step_graph=True,
               out: FitResult | None = None) -> FitResult:
     """lasp_fit_group on device tensors; returns after enqueueing (stream ordered).
     stop_window > 0 turns on the per-spectrum stopping rules (window, stop_tol);
     polish_iters > 0 adds that many Levenberg-Marquardt iterations at most;
     clean_every > 0 turns on the Clean mask updates (every clean_every steps,
     at most clean_max times); n_classes = 3 takes a [60, P + 2M] basis of
-    three emulator temperature classes blended over the Teff regimes."""
+    three emulator temperature classes blended over the Teff regimes;
+    step_graph=False launches every step's kernels instead of replaying the
+    cached graph of 25 steps (same results)."""
     lib = load()
     B, P = obs.shape
     _dev(obs, "obs", torch.float32, (B, P))
@@ -298,7 +303,7 @@ def fit_group(obs, ivar, wave_grid, basis, init_params, n_steps, *, want_cov=Fal
                   eps=eps, weight_quantile=weight_quantile, arms=arms, box=box, stream=stream,
                   stop_window=stop_window, stop_tol=stop_tol, polish_iters=polish_iters,
                   clean_every=clean_every, clean_max=clean_max, n_classes=n_classes,
-                  class_edges=class_edges)
+                  class_edges=class_edges, step_graph=step_graph)
     o.status = ctypes.c_void_p(out.status.data_ptr())
     o.out_chi2 = ctypes.c_void_p(out.chi2.data_ptr())
     if out.steps is not None:

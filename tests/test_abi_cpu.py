@@ -57,6 +57,7 @@ def test_default_opts():
     assert o.lr == pytest.approx(1e-2) and o.beta2 == pytest.approx(0.999)
     assert o.weight_quantile == pytest.approx(0.5)
     assert o.n_classes == 1 and list(o.class_edges) == [4000.0, 4550.0, 7000.0, 9000.0]
+    assert o.step_graph == 1
 
 
 def _call_fit(o, grid, null_obs=False):

@@ -60,3 +60,24 @@ def test_polish_limit_is_flagged_and_fits_are_isolated():
     for i in (0, 5):
         pa, sa = gpu_fit(shape, basis, batch, 20, 8, slice(i, i + 1))
         assert np.array_equal(pa[0], p[i]) and sa[0] == st[i], i
+
+
+def test_plain_lm_with_200_iterations_alone_equals_in_group():
+    """The plain method (no Adam steps, at most 200 LM iterations): the call
+    stops enqueuing iterations once every spectrum has stopped, so a fit
+    alone ends soon after its own stop while in the group the iterations
+    run on until the slowest spectrum stops -- the results must agree bit
+    for bit (a stopped spectrum's iterations change nothing), sit within a
+    tenth of the fit tolerances of the oracle's LM, and none may reach the
+    iteration limit."""
+    print("[LM polish] plain LM, 200 iterations: alone == in group, vs the oracle", flush=True)
+    shape, basis, batch = problem("lamost1550", 8, 61)
+    cfg = oracle.Config.from_shape(shape, BOX_LO, BOX_HI)
+    p, st = gpu_fit(shape, basis, batch, 0, 200)
+    assert not np.any(st & lasp.ST_POLISH_LIMIT), st
+    for i in range(8):
+        pa, sa = gpu_fit(shape, basis, batch, 0, 200, slice(i, i + 1))
+        assert np.array_equal(pa[0], p[i]) and sa[0] == st[i], i
+    ref = oracle.fit_many(cfg, batch.obs, batch.ivar, basis, batch.init)
+    err = np.array([np.abs(p[i] - ref[i]["params"])[:4] for i in range(8)])
+    assert np.all(err <= TIGHT), err
