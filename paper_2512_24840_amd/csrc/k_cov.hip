@@ -21,6 +21,11 @@ namespace {
 
 constexpr int kOffF = 16;
 
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
 struct CovLayout {
   int ks;
   int k_off;   // floats: taps [n_arms][3][ks]
@@ -228,34 +233,50 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
   __syncthreads();  // every read of the staged row is done: sF becomes scratch
   double *scratch = reinterpret_cast<double *>(sF);
 
-  // ---- continuum least squares (as in the fused pass) ---------------------
+  // ---- continuum least squares (as in the fused pass): nu_l = sum W F''^2
+  //      T_l (l <= 2D) and r_n = sum W F'' o T_n (n <= D) from T_0 .. T_D
+  //      only (nu_{D+k} = 2 q_k - nu_{D-k}, q_k = sum W F''^2 T_D T_k); each
+  //      lane sums its pixels in FP32, the sums across lanes and waves are
+  //      FP64 ------------------------------------------------------------------
   {
-    double acc[NMOM];
+    constexpr int D = ND - 1;
+    const float two_over_p = 2.f / (float)P;
+    float nu[ND], q[ND], rr[ND];
 #pragma unroll
-    for (int k = 0; k < NMOM; ++k) acc[k] = 0.0;
-    const double two_over_p = 2.0 / (double)P;
+    for (int k = 0; k < ND; ++k) nu[k] = q[k] = rr[k] = 0.f;
 #pragma unroll
     for (int i = 0; i < kNPL; ++i) {
-      const double x = fma((double)(j0 + i), two_over_p, -1.0);
-      const double wf = (double)ow[i].y * (double)f[i];
-      const double y = wf * (double)f[i];
-      const double z = wf * (double)ow[i].x;
-      double tm = 1.0, tc = x;
-      acc[0] += y;
-      acc[1] = fma(y, x, acc[1]);
-      acc[NNU] += z;
-      acc[NNU + 1] = fma(z, x, acc[NNU + 1]);
+      const float x = fmaf((float)(j0 + i), two_over_p, -1.f);
+      const float wf = ow[i].y * f[i];
+      const float y = wf * f[i];
+      const float z = wf * ow[i].x;
+      const float x2 = x + x;
+      float t[ND];
+      t[0] = 1.f;
+      t[1] = x;
 #pragma unroll
-      for (int l = 2; l < NNU; ++l) {
-        const double tn = fma(x + x, tc, -tm);
-        acc[l] = fma(y, tn, acc[l]);
-        if (l < ND) acc[NNU + l] = fma(z, tn, acc[NNU + l]);
-        tm = tc;
-        tc = tn;
+      for (int l = 2; l < ND; ++l) t[l] = fmaf(x2, t[l - 1], -t[l - 2]);
+      const float yd = y * t[D];
+      nu[0] += y;
+      rr[0] += z;
+#pragma unroll
+      for (int l = 1; l < ND; ++l) {
+        nu[l] = fmaf(y, t[l], nu[l]);
+        q[l] = fmaf(yd, t[l], q[l]);
+        rr[l] = fmaf(z, t[l], rr[l]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    block_sum_lds<NW, NMOM>(acc, scratch, sRed, sMom, lane, wave);
+    float acc[NMOM];  // nu_0..nu_D, q_1..q_D, r_0..r_D
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = nu[k];
+#pragma unroll
+    for (int k = 1; k < ND; ++k) acc[D + k] = q[k];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[NNU + k] = rr[k];
+    block_sum_lds_f32<NW, NMOM>(acc, reinterpret_cast<float *>(scratch), sRed, sW, lane, wave);
+    if (tid < NMOM) sMom[tid] = (tid > D && tid < NNU) ? fma(2.0, sW[tid], -sW[2 * D - tid]) : sW[tid];
+    __syncthreads();
   }
   if (wave == 0) {
     double a[ND + 1];
@@ -303,9 +324,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       opaque(ow[i]);
     }
     const float two_over_p = 2.f / (float)P;
-    double acc[21];
+    float acc[20];  // Ju^T W Ju packed (15), q = Ju^T W e (5): FP32 per lane
 #pragma unroll
-    for (int k = 0; k < 21; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 20; ++k) acc[k] = 0.f;
+    double chi2 = 0.0;
 #pragma unroll
     for (int i = 0; i < kNPL; ++i) {
       const float x = fmaf((float)(j0 + i), two_over_p, -1.f);
@@ -318,31 +340,34 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       }
       const float C = fmaf(x, b1, c[0] - b2);
       const float e = ow[i].x - C * f[i];
-      double dd[kNP];
+      float dd[kNP];
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         // j0 + i < kNPL * BLOCK for every thread; columns are zero where no
         // pixel is
         const float v = sD[t * NCOL + j0 + i] * C;
         sD[t * NCOL + j0 + i] = v;
-        dd[t] = (double)v;
+        dd[t] = v;
       }
       d3[i] *= C;
       d4[i] *= C;
-      dd[3] = (double)d3[i];
-      dd[4] = (double)d4[i];
-      const double w = (double)ow[i].y;
-      const double we = w * (double)e;
+      dd[3] = d3[i];
+      dd[4] = d4[i];
+      const float w = ow[i].y;
+      const float we = w * e;
       int k = 0;
 #pragma unroll
       for (int p = 0; p < kNP; ++p) {
-        const double wd = w * dd[p];
+        const float wd = w * dd[p];
 #pragma unroll
-        for (int q = 0; q <= p; ++q) acc[k++] += wd * dd[q];
+        for (int q = 0; q <= p; ++q) {
+          acc[k] = fmaf(wd, dd[q], acc[k]);
+          ++k;
+        }
       }
 #pragma unroll
-      for (int p = 0; p < kNP; ++p) acc[15 + p] = fma(we, dd[p], acc[15 + p]);
-      acc[20] = fma(we, (double)e, acc[20]);
+      for (int p = 0; p < kNP; ++p) acc[15 + p] = fmaf(we, dd[p], acc[15 + p]);
+      chi2 = fma((double)ow[i].y * (double)e, (double)e, chi2);
       __builtin_amdgcn_sched_barrier(0);
     }
     if (out_jac && has_pix) {
@@ -358,12 +383,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
         }
     }
     if (out_cov == nullptr && out_normal == nullptr) return;
-    block_sum_lds<NW, 21>(acc, scratch, sRed, sJJ, lane, wave);
+    block_sum_lds_f32<NW, 20>(acc, reinterpret_cast<float *>(scratch), sRed, sJJ, lane, wave);
+    double c2[1] = {chi2};
+    block_sum_lds<NW, 1>(c2, scratch, sRed, sJJ + 20, lane, wave);
   }
-  // X[n][t] = Jb^T W Ju = sum W F'' T_n ju_t (Chebyshev T_n).  One pass per
-  // column; the register columns get passes of their own (selecting between
-  // them in one pass would make the compiler keep them in memory).
-  auto xpass = [&](int t, auto column) {
+  // X[n][t] = Jb^T W Ju = sum W F'' T_n ju_t (Chebyshev T_n), FP32 per lane
+  // and FP64 across lanes: one pass for the LDS columns u1..u3 and one for
+  // the register columns mu, sigma, T_0 .. T_D formed once per pixel and pass
+  // (a pass that picked a register column by a run-time index would make
+  // the compiler keep them in memory).
+  auto xpass = [&](auto ncol, int t0, auto column) {
+    constexpr int NCX = decltype(ncol)::value;
     int jb = j0;
     opaque(jb);
 #pragma unroll
@@ -371,33 +401,39 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       opaque(f[i]);
       opaque(ow[i]);
     }
-    double acc[ND];
+    float acc[NCX * ND];  // [column][n]
 #pragma unroll
-    for (int n = 0; n < ND; ++n) acc[n] = 0.0;
-    const double two_over_p = 2.0 / (double)P;
+    for (int n = 0; n < NCX * ND; ++n) acc[n] = 0.f;
+    const float two_over_p = 2.f / (float)P;
 #pragma unroll
     for (int i = 0; i < kNPL; ++i) {
-      const double x = fma((double)(jb + i), two_over_p, -1.0);
-      const double v = (double)ow[i].y * (double)f[i] * (double)column(i);
-      double tm = 1.0, tc = x;
-      acc[0] += v;
-      acc[1] = fma(v, x, acc[1]);
+      const float x = fmaf((float)(jb + i), two_over_p, -1.f);
+      const float x2 = x + x;
+      const float wf = ow[i].y * f[i];
+      float v[NCX];
+#pragma unroll
+      for (int c = 0; c < NCX; ++c) {
+        v[c] = wf * column(c, i);
+        acc[c * ND] += v[c];
+        acc[c * ND + 1] = fmaf(v[c], x, acc[c * ND + 1]);
+      }
+      float tm = 1.f, tc = x;
 #pragma unroll
       for (int n = 2; n < ND; ++n) {
-        const double tn = fma(x + x, tc, -tm);
-        acc[n] = fma(v, tn, acc[n]);
+        const float tn = fmaf(x2, tc, -tm);
+#pragma unroll
+        for (int c = 0; c < NCX; ++c) acc[c * ND + n] = fmaf(v[c], tn, acc[c * ND + n]);
         tm = tc;
         tc = tn;
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    block_sum_lds<NW, ND>(acc, scratch, sRed, sW, lane, wave);
-    if (tid < ND) sX[tid * kNP + t] = sW[tid];
+    block_sum_lds_f32<NW, NCX * ND>(acc, reinterpret_cast<float *>(scratch), sRed, sW, lane, wave);
+    if (tid < NCX * ND) sX[(tid % ND) * kNP + t0 + tid / ND] = sW[tid];
     __syncthreads();
   };
-#pragma unroll 1
-  for (int t = 0; t < 3; ++t) xpass(t, [&](int i) { return sD[t * NCOL + j0 + i]; });
-  xpass(3, [&](int i) { return d3[i]; });
-  xpass(4, [&](int i) { return d4[i]; });
+  xpass(IntC<3>{}, 0, [&](int c, int i) { return sD[c * NCOL + j0 + i]; });
+  xpass(IntC<2>{}, 3, [&](int c, int i) { return c == 0 ? d3[i] : d4[i]; });
 
   // ---- wave 0: Y = A^{-1} X, S = JuJu - X^T Y, Sigma_u = s^2 S^{-1} --------
   if (wave == 0) {
