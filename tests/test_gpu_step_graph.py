@@ -95,3 +95,16 @@ def test_graph_fit_matches_oracle_lm(prob):
     for i in range(batch.obs.shape[0]):
         err = np.abs(got["params"][i].astype(np.float64) - ref[i]["params"])[:4]
         assert np.all(err <= FIT_TOL), (i, err)
+
+
+def test_kernel_timing_launches_every_step(prob):
+    say("[step graph] kernel timing on: every step launched (and timed) on its own")
+    ref = fit(prob, 60, False)
+    lasp.profile_enable(["fused"])
+    try:
+        got = fit(prob, 60, True)
+        n = lasp.profile_read()["fused"][1]
+    finally:
+        lasp.profile_enable([])
+    assert n == 60, n
+    same(got, ref, "timed")
