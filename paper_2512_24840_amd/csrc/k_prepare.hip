@@ -28,28 +28,51 @@ constexpr uint32_t kNoKey = 0xffffffffu;
 
 // k-th smallest (0-based) flux among the valid pixels of one spectrum, by a
 // four-pass 8-bit radix select over the order-preserving keys (staged in
-// LDS, kNoKey for invalid pixels).
+// LDS, kNoKey for invalid pixels).  Each pass counts the candidates' digits
+// into 256 bins (a wave whose candidates all share one digit adds them with
+// one atomic: the first passes see nearly equal fluxes), then thread t
+// takes bin t in a block-wide prefix sum and the one thread whose bin holds
+// the k-th candidate records the digit and the rank within it.
 __device__ float block_select(const uint32_t *keys, int P, uint32_t k, uint32_t *hist,
                               uint32_t *sh) {
-  const int tid = threadIdx.x;
+  static_assert(kPrepBlock == 256, "one bin per thread");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t *wsum = sh + 2;  // [kPrepBlock / 64] bin totals of each wave's bins
   uint32_t prefix = 0, mask = 0;
   for (int shift = 24; shift >= 0; shift -= 8) {
-    for (int i = tid; i < 256; i += kPrepBlock) hist[i] = 0;
+    hist[tid] = 0;
     __syncthreads();
     for (int j = tid; j < P; j += kPrepBlock) {
       const uint32_t key = keys[j];
-      if (key != kNoKey && (key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+      const bool take = key != kNoKey && (key & mask) == prefix;
+      const uint32_t bin = (key >> shift) & 255u;
+      const uint64_t tk = __ballot(take);
+      if (tk == 0) continue;
+      const int first = __ffsll((unsigned long long)tk) - 1;
+      const uint32_t b0 = __shfl(bin, first);
+      if (__ballot(take && bin == b0) == tk) {
+        if (lane == first) atomicAdd(&hist[b0], (uint32_t)__popcll(tk));
+      } else if (take) {
+        atomicAdd(&hist[bin], 1u);
+      }
     }
     __syncthreads();
-    if (tid == 0) {
-      uint32_t cum = 0;
-      int d = 0;
-      for (; d < 255; ++d) {
-        if (cum + hist[d] > k) break;
-        cum += hist[d];
-      }
-      sh[0] = (uint32_t)d;
-      sh[1] = k - cum;
+    const uint32_t h = hist[tid];
+    uint32_t incl = h;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) incl += wsum[w];
+    const uint32_t excl = incl - h;
+    // bins 0..254 hold the k-th candidate when excl <= k < incl; bin 255
+    // takes whatever rank is past bin 254
+    if (excl <= k && (tid == 255 || k < incl)) {
+      sh[0] = (uint32_t)tid;
+      sh[1] = k - excl;
     }
     __syncthreads();
     prefix |= sh[0] << shift;
@@ -70,7 +93,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
   // [max(P, 2 * 64 * kNPL)]: the row's flux keys, then the layout staging
   extern __shared__ __align__(16) uint32_t keys[];
   __shared__ uint32_t hist[256];
-  __shared__ uint32_t sh[2];
+  __shared__ uint32_t sh[2 + kPrepBlock / 64];
   __shared__ int red_n[kPrepBlock / 64];
   __shared__ int red_bad[kPrepBlock / 64];
   const int spec = blockIdx.x;
