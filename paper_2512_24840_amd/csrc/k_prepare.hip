@@ -83,6 +83,33 @@ __device__ float block_select(const uint32_t *keys, int P, uint32_t k, uint32_t 
   return funkey(prefix);
 }
 
+// The (k+1)-th smallest valid flux right after block_select(k) returned key0
+// (its last pass left the digit and the rank in sh[0], sh[1] and the count of
+// that exact key in hist): key0 again if another pixel holds it, else the
+// smallest valid key above key0 -- the same value a second select would
+// give, for one pass over the keys.
+__device__ float block_select_next(const uint32_t *keys, int P, uint32_t key0,
+                                   const uint32_t *hist, uint32_t *sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t *wmin = sh + 2;  // [kPrepBlock / 64]
+  if (sh[1] + 1 < hist[sh[0]]) return funkey(key0);  // block uniform
+  uint32_t m = kNoKey;  // above every valid key
+  for (int j = tid; j < P; j += kPrepBlock) {
+    const uint32_t key = keys[j];
+    if (key > key0) m = min(m, key);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o));
+  __syncthreads();  // every thread has read sh and hist
+  if (lane == 0) wmin[wave] = m;
+  __syncthreads();
+  m = wmin[0];
+#pragma unroll
+  for (int w = 1; w < kPrepBlock / 64; ++w) m = min(m, wmin[w]);
+  __syncthreads();
+  return funkey(m);
+}
+
 __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, const float *obs,
                                                         const float *ivar, const float *init,
                                                         double blo0, double blo1, double blo2,
@@ -135,7 +162,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Geometry g, State s, con
     const float v0 = block_select(keys, g.P, k0, hist, sh);
     float q = v0;
     if (frac > 0.f && k0 + 1 < (uint32_t)n_eff) {
-      const float v1 = block_select(keys, g.P, k0 + 1, hist, sh);
+      const float v1 = block_select_next(keys, g.P, fkey(v0), hist, sh);
       q = v0 + frac * (v1 - v0);
     }
     if (q > 0.f && isfinite(q)) w = exp2f(rintf(log2f(q)));

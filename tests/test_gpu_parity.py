@@ -77,6 +77,31 @@ def test_forward_model_chi2_gradient_match_oracle(name, over):
             (i, grad[i], g_ref)
 
 
+@pytest.mark.parametrize("k", [30, -30])
+def test_results_do_not_depend_on_the_flux_scale_bit_for_bit(k):
+    """The flux weight w is a power of two near the median flux, so scaling
+    obs by 2^k and ivar by 2^-2k scales w by 2^k and leaves every step of the
+    arithmetic unchanged: chi2, J, the gradient and the covariance must agree
+    bit for bit, and the model scale by exactly 2^k.  The rows cover an odd
+    and an even number of valid pixels and fluxes repeated at the median."""
+    say(f"[flux scale] lamost1550 B=6, obs x 2^{k}, ivar x 2^{-2 * k}")
+    shape, cfg, basis, batch = case("lamost1550", 6)
+    obs, ivar = batch.obs.copy(), batch.ivar.copy()
+    obs[0, 200:260] = np.median(obs[0])     # ties at the median
+    ivar[1, :1] = 0.0                        # one pixel fewer: the other parity
+    ivar[2, :3] = 0.0
+    u = to_dev(cfg.normalise(batch.init).astype(np.float32))
+    kw = dict(want_model=True, want_grad=True, want_cov=True, margin=shape.margin,
+              degree=shape.degree)
+    r0 = lasp.forward(to_dev(obs), to_dev(ivar), wave_grid(shape), to_dev(basis), u, **kw)
+    r1 = lasp.forward(to_dev(np.ldexp(obs, k)), to_dev(np.ldexp(ivar, -2 * k)), wave_grid(shape),
+                      to_dev(basis), u, **kw)
+    torch.cuda.synchronize()
+    for key in ("chi2", "J", "grad", "cov", "n_eff", "status"):
+        assert np.array_equal(r0[key].cpu().numpy(), r1[key].cpu().numpy()), key
+    assert np.array_equal(np.ldexp(r0["model"].cpu().numpy(), k), r1["model"].cpu().numpy())
+
+
 def test_model_jacobian_matches_oracle():
     say("[jacobian parity] lamost3900 B=5")
     shape, cfg, basis, batch = case("lamost3900", 5)
